@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: pitch-by-pitch Katsevich reconstruction of the clinical high-pitch workload
+(512^2 x 128 grid, 736 x 64 curved detector, 1160 views/turn x 6 turns, feed 76.8 mm/turn)
+on one MI355X.
+
+One step = one pass of the whole hot path over one synthetic sinogram resident in HBM:
+katsevich_filter (derivative + length weighting, forward rebinning, Hilbert, backward
+rebinning + cosine) followed by katsevich_backproject (PI-window backprojection of every
+pitch with the shared per-pitch tables).  Throughput = (voxel, view) updates with non-zero
+PI coverage per second; volumes/s = 1 / step time.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 work of one (voxel, view) update of the backprojection (FMA = 2 flops):
+# detector row 2, floor/fraction 2, bilinear interpolation 9, PI coverage weight 4,
+# weighted accumulation 3.
+BP_FLOP_PER_UPDATE = 20
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, budget_views=None):
+    """Time the FP64 oracle on one slice of the workload (single thread, BLAS limited to 1
+    thread): filter the views that slice needs, then backproject its 512 x 512 voxels."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    from synth import phantom
+
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    scan = O.Scan(geom)
+    j = gr["nz"] // 4                      # a slice inside pitch 0
+    x = gr["x_first"] + np.arange(gr["nx"]) * gr["dx"]
+    y = gr["y_first"] + np.arange(gr["ny"]) * gr["dy"]
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    z = gr["z_first"] + j * gr["dz"]
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        Li, Lo = O.pi_line(scan, X, Y, np.full(X.shape, z))
+        li, lo, nf, nl = O.pi_view_bounds(scan, Li, Lo)
+        valid = O.valid_mask(scan, nf, nl, O.in_fov(scan, X, Y))
+        a, b = int(nf[valid].min()), int(nl[valid].max())
+        t_plan = time.perf_counter() - t0
+        sino = phantom.project(ph, geom, views=np.arange(a - 1, b + 2)).astype(np.float32)
+        t1 = time.perf_counter()
+        gF = O.filter_views(scan, sino, O.FilterTables(scan))
+        f = O.backproject(scan, gF, a - 1, X[valid], Y[valid], np.full(valid.sum(), z),
+                          li[valid], lo[valid], nf[valid], nl[valid])
+        t = time.perf_counter() - t1 + t_plan
+    updates = int((nl - nf + 1)[valid].sum())
+    return {"value": updates / t / 1e9, "unit": "Gvoxel-view/s", "cores": 1, "kind": "oracle",
+            "sample": f"one 512x512 slice (z index {j}) of the clinical workload: PI lines, "
+                      f"filtering of its {b - a + 1} views and backprojection of "
+                      f"{int(valid.sum())} voxels ({updates:.3e} updates) in {t:.1f} s, "
+                      f"float64 NumPy, 1 thread",
+            "seconds": t, "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "finite": bool(np.isfinite(f).all())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding by pitch ranges is described in the "
+                                   "design notes, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2201_02309_amd as K
+    from synth import configs, gpu_projector, phantom
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = configs.config2()
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    t0 = time.perf_counter()
+    plan = K.Plan(geom, gr, device=0)
+    t_plan = time.perf_counter() - t0
+    info = plan.info
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    sino = gpu_projector.project(ph, geom, device=dev)          # whole scan, resident in HBM
+    n_filt = plan.n_filtered
+    gF = torch.empty((n_filt, geom["det_rows"], geom["det_cols"]), dtype=torch.float32, device=dev)
+    vol = torch.empty((gr["nz"], gr["ny"], gr["nx"]), dtype=torch.float32, device=dev)
+    ws = plan.workspace()
+    print(f"[bench] plan {t_plan:.2f} s, tables {info['table_bytes'] / 2**20:.0f} MiB, "
+          f"workspace {info['workspace_bytes'] / 2**20:.0f} MiB, N_vv {info['n_vv']:.4e}, "
+          f"filtered views {n_filt}", file=sys.stderr, flush=True)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        K.filter_views(plan, sino, out=gF, ws=ws)
+        if ev is not None:
+            ev[1].record()
+        K.backproject(plan, gF, out=vol)
+        if ev is not None:
+            ev[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    filt_ms = [e[0].elapsed_time(e[1]) for e in events]
+    bp_ms = [e[1].elapsed_time(e[2]) for e in events]
+    ms_step = wall * 1e3 / args.steps
+    n_vv = int(info["n_vv"])
+    value = n_vv / (ms_step * 1e-3) / 1e9
+
+    # plain katsevich_recon (the single-call entry point) for comparison
+    for _ in range(2):
+        K.recon(plan, sino, out=vol, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(max(3, args.steps // 2)):
+        K.recon(plan, sino, out=vol, ws=ws)
+    torch.cuda.synchronize()
+    recon_ms = (time.perf_counter() - t1) * 1e3 / max(3, args.steps // 2)
+
+    bp_avg = float(np.mean(bp_ms))
+    achieved = n_vv * BP_FLOP_PER_UPDATE / (bp_avg * 1e-3) / 1e12
+    traffic = None
+    tr_path = os.path.join(ROOT, "profiles", "bp_traffic.json")
+    if os.path.exists(tr_path):
+        with open(tr_path) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == "current":
+            traffic = tr.get("bytes_per_launch")
+    out = {
+        "metric": "Gvoxel-view/s (512^2x128 clinical high-pitch Katsevich recon)",
+        "value": round(value, 3),
+        "unit": "Gvoxel-view/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded ellipsoid phantom, closed-form FP64 line integrals)",
+        "config": {"workload": wl.name, "grid": [gr["nx"], gr["ny"], gr["nz"]],
+                   "voxel_mm": [gr["dx"], gr["dy"], round(gr["dz"], 6)],
+                   "detector": [geom["det_cols"], geom["det_rows"]],
+                   "views": geom["n_views"], "views_per_turn": geom["views_per_turn"],
+                   "feed_mm_per_turn": geom["feed_per_turn"], "n_psi": info["n_psi"],
+                   "pitches": info["n_pitches"], "slices_per_pitch": info["slices_per_pitch"],
+                   "n_vv": n_vv, "filtered_views": n_filt},
+        "volumes_per_s": round(1e3 / ms_step, 3),
+        "stage_ms": {"filter": round(float(np.mean(filt_ms)), 4), "backproject": round(bp_avg, 4)},
+        "recon_call_ms": round(recon_ms, 4),
+        "plan_build_s": round(t_plan, 3),
+        "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+                     "flop_per_update": BP_FLOP_PER_UPDATE},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on one slice (cpu_baseline)", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * katsevich.h -- C ABI of the MI355X (gfx950) pitch-by-pitch Katsevich helical FBP library.
+ *
+ * The library reconstructs f(x) from a helical cone-beam sinogram g(lambda, alpha, w) measured
+ * on a curved detector, following the implementation of Katsevich's inversion formula in
+ * Sec. II of "A three-dimensional dual-domain deep network for high-pitch and sparse helical
+ * CT reconstruction" (Wang et al., arXiv 2201.02309):
+ *   derivative at constant direction (eq. Deriv) -> length-correction weighting (eq. LW) ->
+ *   forward height rebinning onto kappa-lines (eqs. FR, w_k) -> Hilbert transform in alpha
+ *   (eq. HF with the kernel of eq. e4) -> backward height rebinning (eq. BR) -> post-cosine
+ *   weighting (eq. PW) -> backprojection over the PI interval with v*, alpha*, w*
+ *   (backprojection step of Sec. II),
+ * run pitch by pitch with the per-pitch parameters (kappa-rebinning tables, PI limits,
+ * interpolation weights) computed once on the host in float64 and reused for every pitch
+ * (Sec. II periodicity relations and the pre-calculating / reconstruction steps).
+ *
+ * Conventions (all lengths in mm, angles in radians):
+ *   helix      a(lambda) = (R cos(lambda+lambda0), R sin(lambda+lambda0), z0 + P lambda/(2 pi)),
+ *              P = feed_per_turn (Sec. II helix equation);
+ *   views      view n (0 <= n < n_views) at lambda_n = lambda_first + n * 2 pi / views_per_turn;
+ *   detector   curved, radius D about the source; column c at fan angle
+ *              alpha_c = (c - (det_cols-1)/2 + col_offset) * dalpha, row r at height
+ *              w_r = (r - (det_rows-1)/2 + row_offset) * dw (Sec. III-C detector coordinates);
+ *   sinogram   float32 [n_views][det_rows][det_cols], columns fastest;
+ *   volume     voxel (ix,iy,iz) at (x_first+ix*dx, y_first+iy*dy, z_first+iz*dz),
+ *              float32 [nz][ny][nx], x fastest.
+ * Slices repeat every pitch when dz divides P (slices_per_pitch = P/dz); otherwise the
+ * whole grid is one pitch and no table is reused.
+ *
+ * Ownership: the caller allocates every device buffer (tables, sinogram, volume,
+ * workspace) and passes raw device pointers and a hipStream_t (as void*; NULL = the
+ * default stream).  The library never allocates device memory and, except in
+ * katsevich_plan_bind, never synchronises the host: compute calls only enqueue kernels on
+ * the given stream.  A plan is immutable after katsevich_plan_bind; concurrent compute calls
+ * with one bound plan on different streams are safe when their workspaces differ.
+ *
+ * Errors: every int-returning call returns KATS_OK (0) or a negative status; the detail
+ * of the last failure of the calling thread is in katsevich_last_error().  Nothing throws
+ * across the ABI.
+ */
+#ifndef KATSEVICH_H
+#define KATSEVICH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KATS_OK = 0,
+    KATS_EINVAL = -1,            /* a null pointer or an out-of-range argument */
+    KATS_EINVAL_GEOMETRY = -2,   /* geometry / grid rejected (see katsevich_last_error) */
+    KATS_ESHAPE = -3,            /* a buffer size does not match the plan */
+    KATS_EWORKSPACE = -4,        /* workspace smaller than katsevich_plan_info says */
+    KATS_ENOTBOUND = -5,         /* compute call on a plan without device tables */
+    KATS_EHIP = -6,              /* a HIP runtime call or kernel launch failed */
+    KATS_ENOMEM = -7             /* host allocation failed while planning */
+};
+
+/* Scan geometry (Sec. II helix, Sec. III-C detector coordinates).  R: source radius;
+ * D: source-to-detector distance (radius of the curved detector); feed_per_turn: table
+ * feed P per turn (the pitch); lambda0, z0: helix start angle / height; lambda_first:
+ * lambda of view 0; dalpha, dw: detector column (radians) and row (mm) spacing;
+ * col_offset, row_offset: detector offsets in cells; n_views: acquired views;
+ * views_per_turn: views per 2 pi (an integer, so views repeat every turn). */
+typedef struct katsevich_geometry {
+    double R, D, feed_per_turn, lambda0, z0, lambda_first;
+    double dalpha, col_offset, dw, row_offset;
+    int64_t n_views;
+    int32_t views_per_turn, det_cols, det_rows, reserved;
+} katsevich_geometry;
+
+/* Voxel grid, see the volume convention above. */
+typedef struct katsevich_grid {
+    double dx, dy, dz, x_first, y_first, z_first;
+    int32_t nx, ny, nz, reserved;
+} katsevich_grid;
+
+/* Plan options.  n_psi: number of kappa-lines sampled uniformly on
+ * [-pi/2-alpha_m, pi/2+alpha_m] (eq. FR range; 0 -> 2*det_rows+1; must be >= 3);
+ * n_threads: host threads used to build the plan (0 -> all hardware threads). */
+typedef struct katsevich_options {
+    int32_t n_psi, n_threads, flags, reserved;
+} katsevich_options;
+
+typedef struct katsevich_plan_s *katsevich_plan_t;
+
+/* Sizes and counts of a plan. */
+typedef struct katsevich_plan_info {
+    uint64_t table_bytes;              /* device table buffer for katsevich_plan_bind */
+    uint64_t workspace_bytes;          /* workspace of katsevich_recon */
+    uint64_t filtered_bytes;           /* g^F buffer of katsevich_filter / _backproject */
+    uint64_t workspace_bytes_filter;   /* workspace of katsevich_filter */
+    int64_t first_view, last_view;     /* views filtered: those any valid voxel uses */
+    int64_t n_vv;                      /* (voxel, view) pairs with non-zero PI coverage */
+    int64_t n_valid_voxels;            /* voxels reconstructed (others are written 0) */
+    int32_t n_pitches, slices_per_pitch, n_table_slices, n_psi;
+    int32_t window_views;              /* views of one pitch's lambda window W */
+    int32_t window_lo;                 /* first window view of pitch 0 (may be < 0) */
+    int32_t fft_len, commensurate;     /* Hilbert FFT length; 1 if dz divides P */
+} katsevich_plan_info;
+
+/* Table ids for katsevich_plan_export (host copies, for tests). */
+enum {
+    KATS_TABLE_FR_ROW = 1,     /* int32  [n_psi][cols]  floor of the row coordinate of w_kappa */
+    KATS_TABLE_FR_WEIGHT = 2,  /* double [n_psi][cols]  its fractional part */
+    KATS_TABLE_BR_KAPPA = 3,   /* int32  [rows][cols]   kappa index k0 of psi_hat (<= n_psi-2) */
+    KATS_TABLE_BR_WEIGHT = 4,  /* double [rows][cols]   interpolation weight toward k0+1 */
+    KATS_TABLE_PSI_HAT = 5,    /* double [rows][cols]   psi_hat(alpha_c, w_r) */
+    KATS_TABLE_PI_LI = 6,      /* double [n_table_slices][ny][nx] lambda_i in view units (pitch 0) */
+    KATS_TABLE_PI_LO = 7,      /* double [n_table_slices][ny][nx] lambda_o in view units (pitch 0) */
+    KATS_TABLE_PI_NFIRST = 8,  /* int32  [n_table_slices][ny][nx] first view with coverage > 0 */
+    KATS_TABLE_PI_NLAST = 9,   /* int32  [n_table_slices][ny][nx] last view with coverage > 0 */
+    KATS_TABLE_FOV = 10,       /* uint8  [n_table_slices][ny][nx] inside the field of view */
+    KATS_TABLE_VALID = 11      /* uint8  [nz][ny][nx] voxel reconstructed (else written 0) */
+};
+
+/* Build a plan on the host in float64: validates the geometry (rows must cover the
+ * Tam-Danielsson window w_bot(alpha) <= w <= w_top(alpha) over every column, |alpha| <
+ * pi/2, positive sizes), computes the kappa-line forward-rebinning table (eqs. FR, w_k),
+ * psi_hat and the backward-rebinning table (eq. BR; root of smallest |psi| on the
+ * monotone branch), the PI-line limits of every voxel of the first pitch (pre-calculating
+ * step 2), the pitch window (eq. maxvalue), the per-view trigonometry and the Hilbert
+ * kernel spectrum.  *out receives a new plan to be freed with katsevich_plan_destroy.
+ * opts may be NULL (defaults).  Errors: KATS_EINVAL, KATS_EINVAL_GEOMETRY, KATS_ENOMEM. */
+int katsevich_plan(const katsevich_geometry *geom, const katsevich_grid *grid,
+                   const katsevich_options *opts, katsevich_plan_t *out);
+
+/* Sizes and counts of the plan. */
+int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out);
+
+/* Copy the plan's device tables (table_bytes bytes) into caller-owned device memory
+ * d_tables (256-byte aligned) on stream, then wait for that copy.  The buffer must stay
+ * alive and unchanged while the plan is used.  May be called again to rebind. */
+int katsevich_plan_bind(katsevich_plan_t plan, void *d_tables, uint64_t bytes, void *stream);
+
+/* Copy one host table (KATS_TABLE_*) into host_dst of exactly the table's size in bytes
+ * (KATS_ESHAPE otherwise).  Used by tests to compare integer tables bit for bit. */
+int katsevich_plan_export(katsevich_plan_t plan, int which, void *host_dst, uint64_t bytes);
+
+/* Reconstruct: d_sino float32 [n_views][rows][cols] -> d_vol float32 [nz][ny][nx].
+ * Invalid voxels are written 0.  d_ws: device workspace of at least workspace_bytes
+ * (256-byte aligned).  Asynchronous on stream.  Errors: KATS_EINVAL, KATS_ENOTBOUND,
+ * KATS_EWORKSPACE, KATS_EHIP. */
+int katsevich_recon(katsevich_plan_t plan, const float *d_sino, float *d_vol,
+                    void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* Filtering stage alone (eqs. Deriv, LW, FR, HF, BR, PW): d_sino -> d_gF float32
+ * [last_view-first_view+1][rows][cols] holding g^F of views first_view..last_view.
+ * d_ws: at least workspace_bytes_filter.  Asynchronous on stream. */
+int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF,
+                     void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* Backprojection stage alone (backprojection step of Sec. II, every pitch reusing the
+ * first pitch's tables): d_gF as written by katsevich_filter -> d_vol.  Asynchronous. */
+int katsevich_backproject(katsevich_plan_t plan, const float *d_gF, float *d_vol, void *stream);
+
+/* Exact adjoint of katsevich_recon (transpose of the discrete operator): d_grad_vol
+ * float32 [nz][ny][nx] -> d_grad_sino float32 [n_views][rows][cols] (overwritten).
+ * d_ws: at least workspace_bytes.  Asynchronous on stream. */
+int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, float *d_grad_sino,
+                             void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* Free a plan (NULL is ignored).  Device buffers stay with the caller. */
+void katsevich_plan_destroy(katsevich_plan_t plan);
+
+/* Static description of a status code; never NULL. */
+const char *katsevich_status_string(int status);
+
+/* Detail of the calling thread's last error ("" if none); valid until its next call. */
+const char *katsevich_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KATSEVICH_H */

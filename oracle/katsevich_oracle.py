@@ -158,7 +158,8 @@ def hilbert_matrix(scan: Scan) -> np.ndarray:
 def hilbert(scan: Scan, g3, T=None) -> np.ndarray:
     """g4[..., c] = sum_c' K[c - c'] g3[..., c']."""
     T = hilbert_matrix(scan) if T is None else T
-    return np.asarray(g3) @ T.T
+    g3 = np.asarray(g3)
+    return (g3.reshape(-1, g3.shape[-1]) @ T.T).reshape(g3.shape)
 
 
 # ----------------------------------------------------------------------------------
@@ -243,13 +244,16 @@ class FilterTables:
         self.T = hilbert_matrix(scan)
 
 
-def filter_views(scan: Scan, g, tables: FilterTables | None = None, chunk=256) -> np.ndarray:
+def filter_views(scan: Scan, g, tables: FilterTables | None = None, chunk=256,
+                 progress=None) -> np.ndarray:
     """Steps 1-6 of Sec. II on a block of consecutive views -> g^F (first/last view 0)."""
     tables = tables or FilterTables(scan)
     g = np.asarray(g, dtype=np.float64)
     V = g.shape[0]
     out = np.zeros((V, scan.rows, scan.cols))
     for a in range(1, V - 1, chunk):
+        if progress is not None:
+            progress(a, V)
         b = min(V - 1, a + chunk)
         g2 = derivative_lw(scan, g[a - 1:b + 1])[1:-1]
         g3 = forward_rebin(scan, g2, tables.fr)

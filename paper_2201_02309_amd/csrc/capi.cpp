@@ -1,0 +1,293 @@
+// C ABI of the Katsevich library (include/katsevich.h): argument checks, plan lifetime,
+// workspace carving and the launch sequence on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/katsevich.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+struct katsevich_plan_s {
+    kats::PlanHost P;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const std::string &msg) {
+    g_err = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return KATS_EHIP;
+}
+
+bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+}  // namespace
+
+namespace kats {
+
+KParams make_params(const PlanHost &P) {
+    KParams k{};
+    const katsevich_geometry &g = P.geom;
+    const katsevich_grid &gr = P.grid;
+    k.R = (float)g.R;
+    k.D = (float)g.D;
+    k.inv_dalpha = (float)(1.0 / g.dalpha);
+    k.col_c = (float)(0.5 * (g.det_cols - 1) - g.col_offset);
+    k.inv_dw = (float)(1.0 / g.dw);
+    k.row_c = (float)(0.5 * (g.det_rows - 1) - g.row_offset);
+    k.dz = (float)gr.dz;
+    k.x_first = (float)gr.x_first;
+    k.y_first = (float)gr.y_first;
+    k.dx = (float)gr.dx;
+    k.dy = (float)gr.dy;
+    k.scale = (float)(P.dlam / (2.0 * 3.14159265358979323846));
+    k.inv_2dlam = (float)(1.0 / (2.0 * P.dlam));
+    k.inv_2dalpha = (float)(1.0 / (2.0 * g.dalpha));
+    k.nx = gr.nx;
+    k.ny = gr.ny;
+    k.nz = gr.nz;
+    k.ns = P.ns;
+    k.n_tab = P.n_tab;
+    k.rows = g.det_rows;
+    k.cols = g.det_cols;
+    k.n_psi = P.n_psi;
+    k.fft_len = P.fft_len;
+    int l2 = 0;
+    while ((1 << l2) < P.fft_len) ++l2;
+    k.log2n = l2;
+    k.Nv = g.views_per_turn;
+    k.n_lo = P.n_lo;
+    k.W = P.W;
+    k.n_pitches = P.n_pitches;
+    k.n_views = g.n_views;
+    k.first_view = P.first_view;
+    k.n_filt = P.last_view >= P.first_view ? P.last_view - P.first_view + 1 : 0;
+    const unsigned char *base = static_cast<const unsigned char *>(P.d_tables);
+    const TableLayout &L = P.layout;
+    k.view = reinterpret_cast<const float4 *>(base + L.view);
+    k.fr_row = reinterpret_cast<const int *>(base + L.fr_row);
+    k.fr_w = reinterpret_cast<const float *>(base + L.fr_w);
+    k.br_k = reinterpret_cast<const int *>(base + L.br_k);
+    k.br_w = reinterpret_cast<const float *>(base + L.br_w);
+    k.lw = reinterpret_cast<const float *>(base + L.lw);
+    k.cos_alpha = reinterpret_cast<const float *>(base + L.cos_alpha);
+    k.twiddle = reinterpret_cast<const float2 *>(base + L.twiddle);
+    k.hil_im = reinterpret_cast<const float *>(base + L.hil_im);
+    k.pi = reinterpret_cast<const PiEntry *>(base + L.pi);
+    return k;
+}
+
+hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
+
+}  // namespace kats
+
+extern "C" {
+
+const char *katsevich_status_string(int status) {
+    switch (status) {
+        case KATS_OK: return "ok";
+        case KATS_EINVAL: return "invalid argument";
+        case KATS_EINVAL_GEOMETRY: return "invalid geometry or grid";
+        case KATS_ESHAPE: return "buffer size does not match the plan";
+        case KATS_EWORKSPACE: return "workspace too small";
+        case KATS_ENOTBOUND: return "plan has no bound device tables";
+        case KATS_EHIP: return "HIP runtime error";
+        case KATS_ENOMEM: return "out of host memory";
+        default: return "unknown status";
+    }
+}
+
+const char *katsevich_last_error(void) { return g_err.c_str(); }
+
+int katsevich_plan(const katsevich_geometry *geom, const katsevich_grid *grid,
+                   const katsevich_options *opts, katsevich_plan_t *out) {
+    g_err.clear();
+    if (!geom || !grid || !out) return fail(KATS_EINVAL, "katsevich_plan: null argument");
+    *out = nullptr;
+    katsevich_options o{};
+    if (opts) o = *opts;
+    katsevich_plan_s *p = new (std::nothrow) katsevich_plan_s();
+    if (!p) return fail(KATS_ENOMEM, "katsevich_plan: out of host memory");
+    std::string err;
+    int st;
+    try {
+        st = kats::build_plan(*geom, *grid, o, p->P, err);
+    } catch (const std::bad_alloc &) {
+        st = KATS_ENOMEM;
+        err = "out of host memory while planning";
+    } catch (...) {
+        st = KATS_EINVAL;
+        err = "unexpected failure while planning";
+    }
+    if (st != KATS_OK) {
+        delete p;
+        return fail(st, "katsevich_plan: " + err);
+    }
+    *out = p;
+    return KATS_OK;
+}
+
+int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
+    g_err.clear();
+    if (!plan || !out) return fail(KATS_EINVAL, "katsevich_plan_query: null argument");
+    const kats::PlanHost &P = plan->P;
+    katsevich_plan_info i{};
+    i.table_bytes = P.layout.total;
+    i.workspace_bytes = P.g4_bytes + P.g2_bytes;
+    i.filtered_bytes = P.gF_bytes;
+    i.workspace_bytes_filter = P.g4_bytes + P.g2_bytes;
+    i.first_view = P.first_view;
+    i.last_view = P.last_view;
+    i.n_vv = P.n_vv;
+    i.n_valid_voxels = P.n_valid;
+    i.n_pitches = P.n_pitches;
+    i.slices_per_pitch = P.ns;
+    i.n_table_slices = P.n_tab;
+    i.n_psi = P.n_psi;
+    i.window_views = P.W;
+    i.window_lo = P.n_lo;
+    i.fft_len = P.fft_len;
+    i.commensurate = P.commensurate ? 1 : 0;
+    *out = i;
+    return KATS_OK;
+}
+
+int katsevich_plan_bind(katsevich_plan_t plan, void *d_tables, uint64_t bytes, void *stream) {
+    g_err.clear();
+    if (!plan || !d_tables) return fail(KATS_EINVAL, "katsevich_plan_bind: null argument");
+    kats::PlanHost &P = plan->P;
+    if (bytes < P.layout.total)
+        return fail(KATS_ESHAPE, "katsevich_plan_bind: table buffer smaller than table_bytes");
+    if (!aligned256(d_tables)) return fail(KATS_EINVAL, "katsevich_plan_bind: buffer not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(d_tables, P.image.data(), P.layout.total, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "katsevich_plan_bind: hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "katsevich_plan_bind: hipStreamSynchronize");
+    P.d_tables = d_tables;
+    return KATS_OK;
+}
+
+int katsevich_plan_export(katsevich_plan_t plan, int which, void *host_dst, uint64_t bytes) {
+    g_err.clear();
+    if (!plan || !host_dst) return fail(KATS_EINVAL, "katsevich_plan_export: null argument");
+    const kats::PlanHost &P = plan->P;
+    const void *src = nullptr;
+    uint64_t n = 0;
+    std::vector<uint8_t> valid;
+    switch (which) {
+        case KATS_TABLE_FR_ROW: src = P.fr_row.data(); n = P.fr_row.size() * 4; break;
+        case KATS_TABLE_FR_WEIGHT: src = P.fr_w.data(); n = P.fr_w.size() * 8; break;
+        case KATS_TABLE_BR_KAPPA: src = P.br_k.data(); n = P.br_k.size() * 4; break;
+        case KATS_TABLE_BR_WEIGHT: src = P.br_w.data(); n = P.br_w.size() * 8; break;
+        case KATS_TABLE_PSI_HAT: src = P.psi_hat.data(); n = P.psi_hat.size() * 8; break;
+        case KATS_TABLE_PI_LI: src = P.pi_li.data(); n = P.pi_li.size() * 8; break;
+        case KATS_TABLE_PI_LO: src = P.pi_lo.data(); n = P.pi_lo.size() * 8; break;
+        case KATS_TABLE_PI_NFIRST: src = P.pi_nf.data(); n = P.pi_nf.size() * 4; break;
+        case KATS_TABLE_PI_NLAST: src = P.pi_nl.data(); n = P.pi_nl.size() * 4; break;
+        case KATS_TABLE_FOV: src = P.fov.data(); n = P.fov.size(); break;
+        case KATS_TABLE_VALID: {
+            const katsevich_grid &gr = P.grid;
+            valid.resize((size_t)gr.nz * gr.ny * gr.nx);
+            for (int iz = 0; iz < gr.nz; ++iz)
+                for (int iy = 0; iy < gr.ny; ++iy)
+                    for (int ix = 0; ix < gr.nx; ++ix)
+                        valid[((size_t)iz * gr.ny + iy) * gr.nx + ix] = kats::voxel_valid(P, iz, iy, ix) ? 1 : 0;
+            src = valid.data();
+            n = valid.size();
+            break;
+        }
+        default: return fail(KATS_EINVAL, "katsevich_plan_export: unknown table id");
+    }
+    if (bytes != n) return fail(KATS_ESHAPE, "katsevich_plan_export: size mismatch (need " + std::to_string(n) + ")");
+    std::memcpy(host_dst, src, n);
+    return KATS_OK;
+}
+
+static int check_compute(katsevich_plan_t plan, const void *a, const void *b, const char *who) {
+    if (!plan || !a || !b) return fail(KATS_EINVAL, std::string(who) + ": null argument");
+    if (!plan->P.d_tables) return fail(KATS_ENOTBOUND, std::string(who) + ": plan not bound");
+    return KATS_OK;
+}
+
+int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF, void *d_ws,
+                     uint64_t ws_bytes, void *stream) {
+    g_err.clear();
+    int st = check_compute(plan, d_sino, d_gF, "katsevich_filter");
+    if (st) return st;
+    const kats::PlanHost &P = plan->P;
+    if (P.g4_bytes + P.g2_bytes > 0 && (!d_ws || ws_bytes < P.g4_bytes + P.g2_bytes))
+        return fail(KATS_EWORKSPACE, "katsevich_filter: workspace too small");
+    if (d_ws && !aligned256(d_ws)) return fail(KATS_EINVAL, "katsevich_filter: workspace not 256-byte aligned");
+    const kats::KParams k = kats::make_params(P);
+    float *g4 = static_cast<float *>(d_ws);
+    float *g2 = reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + P.g4_bytes);
+    hipError_t e = kats::launch_filter(k, d_sino, g2, g4, d_gF, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_filter: launch");
+    return KATS_OK;
+}
+
+int katsevich_backproject(katsevich_plan_t plan, const float *d_gF, float *d_vol, void *stream) {
+    g_err.clear();
+    int st = check_compute(plan, d_gF, d_vol, "katsevich_backproject");
+    if (st) return st;
+    const kats::KParams k = kats::make_params(plan->P);
+    hipError_t e = kats::launch_backproject(k, d_gF, d_vol, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_backproject: launch");
+    return KATS_OK;
+}
+
+int katsevich_recon(katsevich_plan_t plan, const float *d_sino, float *d_vol, void *d_ws,
+                    uint64_t ws_bytes, void *stream) {
+    g_err.clear();
+    int st = check_compute(plan, d_sino, d_vol, "katsevich_recon");
+    if (st) return st;
+    const kats::PlanHost &P = plan->P;
+    if (P.g4_bytes + P.g2_bytes > 0 && (!d_ws || ws_bytes < P.g4_bytes + P.g2_bytes))
+        return fail(KATS_EWORKSPACE, "katsevich_recon: workspace too small");
+    if (d_ws && !aligned256(d_ws)) return fail(KATS_EINVAL, "katsevich_recon: workspace not 256-byte aligned");
+    const kats::KParams k = kats::make_params(P);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *g4 = static_cast<float *>(d_ws);
+    float *g2 = reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + P.g4_bytes);
+    // g^F overwrites g2 (consumed by the Hilbert stage before the backward rebinning runs)
+    hipError_t e = kats::launch_filter(k, d_sino, g2, g4, g2, s);
+    if (e != hipSuccess) return hip_fail(e, "katsevich_recon: filter launch");
+    e = kats::launch_backproject(k, g2, d_vol, s);
+    if (e != hipSuccess) return hip_fail(e, "katsevich_recon: backprojection launch");
+    return KATS_OK;
+}
+
+int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, float *d_grad_sino,
+                             void *d_ws, uint64_t ws_bytes, void *stream) {
+    g_err.clear();
+    int st = check_compute(plan, d_grad_vol, d_grad_sino, "katsevich_recon_backward");
+    if (st) return st;
+    const kats::PlanHost &P = plan->P;
+    if (P.g4_bytes + P.g2_bytes > 0 && (!d_ws || ws_bytes < P.g4_bytes + P.g2_bytes))
+        return fail(KATS_EWORKSPACE, "katsevich_recon_backward: workspace too small");
+    if (d_ws && !aligned256(d_ws)) return fail(KATS_EINVAL, "katsevich_recon_backward: workspace not 256-byte aligned");
+    const kats::KParams k = kats::make_params(P);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *g4 = static_cast<float *>(d_ws);
+    float *g2 = reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + P.g4_bytes);
+    hipError_t e = kats::launch_zero(g2, P.g2_bytes, s);
+    if (e == hipSuccess) e = kats::launch_backproject_T(k, d_grad_vol, g2, s);
+    if (e == hipSuccess) e = kats::launch_filter_T(k, g2, g4, g2, d_grad_sino, s);
+    if (e != hipSuccess) return hip_fail(e, "katsevich_recon_backward: launch");
+    return KATS_OK;
+}
+
+void katsevich_plan_destroy(katsevich_plan_t plan) { delete plan; }
+
+}  // extern "C"

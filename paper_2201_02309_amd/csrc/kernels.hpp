@@ -1,0 +1,53 @@
+// Kernel parameter block and launchers of the gfx950 Katsevich kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace kats {
+
+// Scalars and table pointers every kernel reads; passed by value (kernel argument).
+struct KParams {
+    // detector / geometry (float32 copies of float64 plan values)
+    float R, D;
+    float inv_dalpha, col_c;      // column coordinate = alpha * inv_dalpha + col_c
+    float inv_dw, row_c;          // row coordinate    = w * inv_dw + row_c
+    float dz;
+    float x_first, y_first, dx, dy;
+    float scale;                  // dlambda / (2 pi)
+    float inv_2dlam, inv_2dalpha;
+    int nx, ny, nz, ns, n_tab;
+    int rows, cols, n_psi, fft_len, log2n;
+    int Nv, n_lo, W, n_pitches;
+    long long n_views, first_view, n_filt;
+    // device tables (inside the caller's bound table buffer)
+    const float4 *view;
+    const int *fr_row;
+    const float *fr_w;
+    const int *br_k;
+    const float *br_w;
+    const float *lw;
+    const float *cos_alpha;
+    const float2 *twiddle;
+    const float *hil_im;
+    const PiEntry *pi;
+};
+
+KParams make_params(const PlanHost &P);
+
+// Forward filter chain on views first_view..last_view:
+//   g2 = deriv+LW(sino); g4 = Hilbert(FR(g2)); gF = cos * BR(g4).
+hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,
+                         hipStream_t s);
+// Backprojection of every pitch (reusing the first pitch's tables).
+hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s);
+
+// Adjoint pieces.
+hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFbar, hipStream_t s);
+hipError_t launch_filter_T(const KParams &k, const float *gFbar, float *g4bar, float *g2bar,
+                           float *gsino, hipStream_t s);
+
+}  // namespace kats

@@ -1,0 +1,417 @@
+// Host float64 plan builder: see plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <thread>
+
+namespace kats {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+
+// ---------------------------------------------------------------------------------
+// kappa-lines (eqs. FR and w_k; R_o read as R, P as the feed per turn)
+// ---------------------------------------------------------------------------------
+struct Kappa {
+    double scale;   // D P / (2 pi R)
+    double wk(double a, double p) const {
+        const double pc = (p == 0.0) ? 1.0 : p / std::tan(p);   // psi cot psi -> 1 at 0
+        return scale * (p * std::cos(a) + pc * std::sin(a));
+    }
+    // d w_kappa / d psi; the bracket is psi-derivative of psi cot psi
+    double dwk(double a, double p) const {
+        const double s = std::sin(p);
+        return scale * (std::cos(a) + std::sin(a) * (std::cos(p) / s - p / (s * s)));
+    }
+};
+
+// Bisection for an increasing function on [lo, hi], run to the end of float64
+// resolution (until the midpoint no longer lies strictly inside the bracket).
+template <class F>
+double bisect_increasing(F f, double lo, double hi) {
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        const double v = f(mid);
+        if (v < 0) lo = mid;
+        else if (v > 0) hi = mid;
+        else { lo = hi = mid; break; }
+    }
+    return 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------------------------
+// PI lines.  For source angle b1 = s + lambda0 the in-plane chord through X = (x, y)
+// ends at b1 + 2 theta with tan(theta) = (R - rho cos(phi - b1)) / (rho sin(phi - b1))
+// (the chord's distance to the axis is R cos(theta) and its normal points at
+// b1 + theta); X sits at fraction t = (X - S1).(S2 - S1) / |S2 - S1|^2 along it.
+// lambda_i = s solves z0 + h (s + t * 2 theta) = z.
+// ---------------------------------------------------------------------------------
+struct PiSolver {
+    double R, h, lambda0, z0;
+
+    void chord(double s, double x, double y, double &span, double &t) const {
+        const double b1 = s + lambda0;
+        const double rho = std::hypot(x, y);
+        const double phi = std::atan2(y, x);
+        const double d = phi - b1;
+        const double th = std::atan2(R - rho * std::cos(d), rho * std::sin(d));   // (0, pi)
+        span = 2.0 * th;
+        const double c1 = std::cos(b1), s1 = std::sin(b1);
+        const double c2 = std::cos(b1 + span), s2 = std::sin(b1 + span);
+        const double ex = R * (c2 - c1), ey = R * (s2 - s1);
+        t = ((x - R * c1) * ex + (y - R * s1) * ey) / (ex * ex + ey * ey);
+    }
+
+    double height_gap(double s, double x, double y, double z) const {
+        double span, t;
+        chord(s, x, y, span, t);
+        return z0 + h * (s + t * span) - z;
+    }
+
+    // Illinois-modified regula falsi on the bracket ((z-z0)/h - 2pi, (z-z0)/h).
+    void solve(double x, double y, double z, double &li, double &lo) const {
+        const double zr = (z - z0) / h;
+        double a = zr - kTwoPi, b = zr;
+        double fa = height_gap(a, x, y, z), fb = height_gap(b, x, y, z);
+        double s = 0.5 * (a + b);
+        int side = 0;
+        for (int it = 0; it < 200; ++it) {
+            if (!(fa < 0 && fb > 0)) break;
+            s = b - fb * (b - a) / (fb - fa);
+            if (!(s > a && s < b)) s = 0.5 * (a + b);
+            if (!(s > a && s < b)) break;                 // bracket at float64 resolution
+            const double fs = height_gap(s, x, y, z);
+            if (fs == 0.0) { a = b = s; break; }
+            if (fs < 0) {
+                a = s; fa = fs;
+                if (side == -1) fb *= 0.5;
+                side = -1;
+            } else {
+                b = s; fb = fs;
+                if (side == +1) fa *= 0.5;
+                side = +1;
+            }
+            if (b - a <= 4e-16 * std::max(1.0, std::fabs(s))) break;
+        }
+        s = (a == b) ? a : s;
+        double span, t;
+        chord(s, x, y, span, t);
+        li = s;
+        lo = s + span;
+    }
+};
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+int threads_for(const katsevich_options &o) {
+    int n = o.n_threads > 0 ? o.n_threads : (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(n, 256));
+}
+
+template <class Fn>
+void parallel_for(int n, int threads, Fn fn) {
+    std::atomic<int> next(0);
+    auto worker = [&]() {
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= n) break;
+            fn(i);
+        }
+    };
+    std::vector<std::thread> pool;
+    const int t = std::min(threads, n);
+    for (int k = 1; k < t; ++k) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
+}
+
+}  // namespace
+
+bool voxel_valid(const PlanHost &P, int iz, int iy, int ix) {
+    const int k = iz / P.ns, j = iz % P.ns;
+    const size_t e = ((size_t)j * P.grid.ny + iy) * P.grid.nx + ix;
+    if (!P.fov[e]) return false;
+    const int64_t shift = (int64_t)k * P.geom.views_per_turn;
+    return P.pi_nf[e] + shift - 1 >= 0 && P.pi_nl[e] + shift + 1 <= P.geom.n_views - 1;
+}
+
+int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
+               const katsevich_options &opts, PlanHost &P, std::string &err) {
+    P.geom = g;
+    P.grid = gr;
+    P.opts = opts;
+    // ------------------------------------------------------------------ validation
+    auto bad = [&](const std::string &m) { err = m; return KATS_EINVAL_GEOMETRY; };
+    if (!(g.R > 0) || !(g.D > 0) || !(g.feed_per_turn > 0)) return bad("R, D and feed_per_turn must be > 0");
+    if (g.views_per_turn < 4) return bad("views_per_turn must be >= 4");
+    if (g.n_views < 3) return bad("n_views must be >= 3");
+    if (g.det_cols < 2 || g.det_rows < 2) return bad("detector needs >= 2 columns and rows");
+    if (g.det_cols > 1024) return bad("det_cols > 1024 is not supported (Hilbert FFT length <= 2048)");
+    if (!(g.dalpha > 0) || !(g.dw > 0)) return bad("dalpha and dw must be > 0");
+    if (gr.nx < 1 || gr.ny < 1 || gr.nz < 1) return bad("grid sizes must be >= 1");
+    if (!(gr.dx > 0) || !(gr.dy > 0) || !(gr.dz > 0)) return bad("grid spacings must be > 0");
+    if (opts.n_psi != 0 && opts.n_psi < 3) return bad("n_psi must be 0 or >= 3");
+
+    const int cols = g.det_cols, rows = g.det_rows;
+    P.h = g.feed_per_turn / kTwoPi;
+    P.dlam = kTwoPi / g.views_per_turn;
+    P.alpha.resize(cols);
+    P.w.resize(rows);
+    for (int c = 0; c < cols; ++c) P.alpha[c] = (c - 0.5 * (cols - 1) + g.col_offset) * g.dalpha;
+    for (int r = 0; r < rows; ++r) P.w[r] = (r - 0.5 * (rows - 1) + g.row_offset) * g.dw;
+    const double a_first = P.alpha.front(), a_last = P.alpha.back();
+    if (!(a_first < 0 && a_last > 0)) return bad("detector columns must straddle alpha = 0");
+    if (!(a_last < 0.5 * kPi && -a_first < 0.5 * kPi)) return bad("|alpha| must stay below pi/2");
+    P.alpha_m = std::max(std::fabs(a_first), std::fabs(a_last));
+    P.r_fov = g.R * std::sin(std::min(-a_first, a_last));
+
+    // Tam-Danielsson window of the curved detector: w_top(a) = (D P/2pi R)(pi/2 - a)/cos a,
+    // w_bot(a) = -(D P/2pi R)(pi/2 + a)/cos a, must lie inside the row range.
+    const Kappa K{g.D * P.h / g.R};
+    for (int c = 0; c < cols; ++c) {
+        const double a = P.alpha[c];
+        const double top = K.scale * (0.5 * kPi - a) / std::cos(a);
+        const double bot = -K.scale * (0.5 * kPi + a) / std::cos(a);
+        if (top > P.w.back() || bot < P.w.front()) {
+            return bad("detector rows do not cover the Tam-Danielsson window (need w from " +
+                       std::to_string(bot) + " to " + std::to_string(top) + " mm at column " +
+                       std::to_string(c) + ")");
+        }
+    }
+
+    // ------------------------------------------------------------------ kappa-lines
+    P.n_psi = opts.n_psi ? opts.n_psi : 2 * rows + 1;
+    P.psi_max = 0.5 * kPi + P.alpha_m;
+    P.dpsi = 2.0 * P.psi_max / (P.n_psi - 1);
+    P.psi.resize(P.n_psi);
+    for (int k = 0; k < P.n_psi; ++k) P.psi[k] = (k - 0.5 * (P.n_psi - 1)) * P.dpsi;
+
+    P.fr_row.resize((size_t)P.n_psi * cols);
+    P.fr_w.resize((size_t)P.n_psi * cols);
+    for (int k = 0; k < P.n_psi; ++k)
+        for (int c = 0; c < cols; ++c) {
+            const double s = K.wk(P.alpha[c], P.psi[k]) / g.dw + 0.5 * (rows - 1) - g.row_offset;
+            const double f = std::floor(s);
+            P.fr_row[(size_t)k * cols + c] = (int32_t)f;
+            P.fr_w[(size_t)k * cols + c] = s - f;
+        }
+
+    // psi_hat: root of w = w_kappa(alpha, psi) on the branch through psi = 0 where
+    // w_kappa increases; the branch ends at a turning point (d w_kappa/d psi = 0) or at
+    // +-psi_max.  d w_kappa/d psi decreases in |psi| on the side where sin(alpha) psi > 0.
+    P.psi_hat.resize((size_t)rows * cols);
+    P.br_k.resize((size_t)rows * cols);
+    P.br_w.resize((size_t)rows * cols);
+    for (int c = 0; c < cols; ++c) {
+        const double a = P.alpha[c];
+        double lo = -P.psi_max, hi = P.psi_max;
+        if (a > 0 && K.dwk(a, P.psi_max) < 0)
+            hi = bisect_increasing([&](double p) { return -K.dwk(a, p); }, 1e-3, P.psi_max);
+        if (a < 0 && K.dwk(a, -P.psi_max) < 0)
+            lo = bisect_increasing([&](double p) { return K.dwk(a, p); }, -P.psi_max, -1e-3);
+        const double wlo = K.wk(a, lo), whi = K.wk(a, hi);
+        for (int r = 0; r < rows; ++r) {
+            const double wr = P.w[r];
+            double ph;
+            if (wr <= wlo) ph = lo;
+            else if (wr >= whi) ph = hi;
+            else ph = bisect_increasing([&](double p) { return K.wk(a, p) - wr; }, lo, hi);
+            double q = ph / P.dpsi + 0.5 * (P.n_psi - 1);
+            q = std::min(std::max(q, 0.0), (double)(P.n_psi - 1));
+            const double k0 = std::min(std::floor(q), (double)(P.n_psi - 2));
+            const size_t e = (size_t)r * cols + c;
+            P.psi_hat[e] = ph;
+            P.br_k[e] = (int32_t)k0;
+            P.br_w[e] = q - k0;
+        }
+    }
+
+    // ------------------------------------------------------------------ pitches
+    const int ns_round = (int)std::llround(g.feed_per_turn / gr.dz);
+    if (ns_round >= 1 && std::fabs(ns_round * gr.dz - g.feed_per_turn) <= 1e-9 * g.feed_per_turn) {
+        P.commensurate = true;
+        P.ns = ns_round;
+    } else {
+        P.commensurate = false;
+        P.ns = gr.nz;
+    }
+    P.n_tab = std::min(P.ns, gr.nz);
+    P.n_pitches = (gr.nz + P.ns - 1) / P.ns;
+
+    // ------------------------------------------------------------------ PI limits
+    const size_t plane = (size_t)gr.ny * gr.nx;
+    const size_t nvox = (size_t)P.n_tab * plane;
+    try {
+        P.pi_li.resize(nvox);
+        P.pi_lo.resize(nvox);
+        P.pi_nf.resize(nvox);
+        P.pi_nl.resize(nvox);
+        P.fov.resize(nvox);
+    } catch (...) {
+        err = "out of host memory for PI tables";
+        return KATS_ENOMEM;
+    }
+    const PiSolver S{g.R, P.h, g.lambda0, g.z0};
+    const double r2 = P.r_fov * P.r_fov;
+    parallel_for(P.n_tab * gr.ny, threads_for(opts), [&](int jy) {
+        const int j = jy / gr.ny, iy = jy % gr.ny;
+        const double z = gr.z_first + j * gr.dz;
+        const double y = gr.y_first + iy * gr.dy;
+        for (int ix = 0; ix < gr.nx; ++ix) {
+            const double x = gr.x_first + ix * gr.dx;
+            const size_t e = (size_t)j * plane + (size_t)iy * gr.nx + ix;
+            double li, lo;
+            S.solve(x, y, z, li, lo);
+            const double vi = (li - g.lambda_first) / P.dlam;
+            const double vo = (lo - g.lambda_first) / P.dlam;
+            P.pi_li[e] = vi;
+            P.pi_lo[e] = vo;
+            P.pi_nf[e] = (int32_t)(std::floor(vi - 0.5) + 1.0);
+            P.pi_nl[e] = (int32_t)(std::ceil(vo + 0.5) - 1.0);
+            P.fov[e] = (x * x + y * y <= r2) ? 1 : 0;
+        }
+    });
+
+    int64_t nmin = std::numeric_limits<int64_t>::max(), nmax = std::numeric_limits<int64_t>::min();
+    for (size_t e = 0; e < nvox; ++e)
+        if (P.fov[e]) {
+            nmin = std::min<int64_t>(nmin, P.pi_nf[e]);
+            nmax = std::max<int64_t>(nmax, P.pi_nl[e]);
+        }
+    if (nmin > nmax) return bad("no voxel of the grid lies inside the field of view");
+    P.n_lo = (int32_t)(nmin - 1);
+    P.n_hi = (int32_t)(nmax + 1);
+    P.W = P.n_hi - P.n_lo + 1;
+
+    // valid voxels, (voxel, view) pairs, filtered view range
+    P.n_vv = 0;
+    P.n_valid = 0;
+    int64_t vmin = std::numeric_limits<int64_t>::max(), vmax = std::numeric_limits<int64_t>::min();
+    for (int iz = 0; iz < gr.nz; ++iz) {
+        const int k = iz / P.ns, j = iz % P.ns;
+        const int64_t shift = (int64_t)k * g.views_per_turn;
+        for (size_t q = 0; q < plane; ++q) {
+            const size_t e = (size_t)j * plane + q;
+            if (!P.fov[e]) continue;
+            const int64_t nf = P.pi_nf[e] + shift, nl = P.pi_nl[e] + shift;
+            if (nf - 1 < 0 || nl + 1 > g.n_views - 1) continue;
+            P.n_valid += 1;
+            P.n_vv += nl - nf + 1;
+            vmin = std::min(vmin, nf);
+            vmax = std::max(vmax, nl);
+        }
+    }
+    if (P.n_valid == 0) {
+        P.first_view = 1;
+        P.last_view = 0;   // empty
+    } else {
+        P.first_view = vmin;
+        P.last_view = vmax;
+    }
+
+    // ------------------------------------------------------------------ Hilbert spectrum
+    // taps K[m] = 2 dalpha / (pi sin(m dalpha)) for odd m, 0 for even m; real and odd, so the
+    // length-N DFT of the wrapped taps is i * Im with Im[f] = -2 sum_{m odd} K[m] sin(2 pi f m/N).
+    P.fft_len = 1;
+    while (P.fft_len < 2 * cols - 1) P.fft_len *= 2;
+    P.fft_len = std::max(P.fft_len, 16);
+    const int N = P.fft_len;
+    P.hil_im.assign(N, 0.0);
+    for (int f = 0; f < N; ++f) {
+        double acc = 0.0;
+        for (int m = 1; m < cols; m += 2) {
+            const double Km = 2.0 * g.dalpha / (kPi * std::sin(m * g.dalpha));
+            const long long ph = ((long long)f * m) % N;
+            acc += Km * std::sin(kTwoPi * (double)ph / N);
+        }
+        P.hil_im[f] = -2.0 * acc / N;
+    }
+
+    // ------------------------------------------------------------------ device image
+    TableLayout &L = P.layout;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
+    L.view = take((uint64_t)P.W * 16);
+    L.fr_row = take((uint64_t)P.n_psi * cols * 4);
+    L.fr_w = take((uint64_t)P.n_psi * cols * 4);
+    L.br_k = take((uint64_t)rows * cols * 4);
+    L.br_w = take((uint64_t)rows * cols * 4);
+    L.lw = take((uint64_t)rows * 4);
+    L.cos_alpha = take((uint64_t)cols * 4);
+    L.twiddle = take((uint64_t)N * 8);
+    L.hil_im = take((uint64_t)N * 4);
+    L.pi = take((uint64_t)nvox * sizeof(PiEntry));
+    L.total = off;
+    try {
+        P.image.assign(L.total, 0);
+    } catch (...) {
+        err = "out of host memory for the device table image";
+        return KATS_ENOMEM;
+    }
+    unsigned char *img = P.image.data();
+    {
+        float *v = reinterpret_cast<float *>(img + L.view);
+        for (int m = 0; m < P.W; ++m) {
+            const double lam = g.lambda_first + (double)(P.n_lo + m) * P.dlam;
+            const double b = lam + g.lambda0;
+            v[4 * m + 0] = (float)std::cos(b);
+            v[4 * m + 1] = (float)std::sin(b);
+            v[4 * m + 2] = (float)(gr.z_first - g.z0 - P.h * lam);
+            v[4 * m + 3] = 0.0f;
+        }
+    }
+    std::memcpy(img + L.fr_row, P.fr_row.data(), P.fr_row.size() * 4);
+    {
+        float *d = reinterpret_cast<float *>(img + L.fr_w);
+        for (size_t i = 0; i < P.fr_w.size(); ++i) d[i] = (float)P.fr_w[i];
+    }
+    std::memcpy(img + L.br_k, P.br_k.data(), P.br_k.size() * 4);
+    {
+        float *d = reinterpret_cast<float *>(img + L.br_w);
+        for (size_t i = 0; i < P.br_w.size(); ++i) d[i] = (float)P.br_w[i];
+        float *lw = reinterpret_cast<float *>(img + L.lw);
+        for (int r = 0; r < rows; ++r) lw[r] = (float)(g.D / std::sqrt(g.D * g.D + P.w[r] * P.w[r]));
+        float *ca = reinterpret_cast<float *>(img + L.cos_alpha);
+        for (int c = 0; c < cols; ++c) ca[c] = (float)std::cos(P.alpha[c]);
+        float *tw = reinterpret_cast<float *>(img + L.twiddle);
+        for (int k = 0; k < N; ++k) {
+            tw[2 * k + 0] = (float)std::cos(kTwoPi * k / N);
+            tw[2 * k + 1] = (float)(-std::sin(kTwoPi * k / N));
+        }
+        float *hi = reinterpret_cast<float *>(img + L.hil_im);
+        for (int f = 0; f < N; ++f) hi[f] = (float)P.hil_im[f];
+    }
+    {
+        PiEntry *pe = reinterpret_cast<PiEntry *>(img + L.pi);
+        constexpr int32_t kEmptyLo = 1 << 29;
+        for (size_t e = 0; e < nvox; ++e) {
+            if (P.fov[e]) {
+                pe[e].li = (float)(P.pi_li[e] - P.n_lo);
+                pe[e].lo = (float)(P.pi_lo[e] - P.n_lo);
+                pe[e].nf = P.pi_nf[e] - P.n_lo;
+                pe[e].nl = P.pi_nl[e] - P.n_lo;
+            } else {
+                pe[e].li = 0.f;
+                pe[e].lo = 0.f;
+                pe[e].nf = kEmptyLo;
+                pe[e].nl = -kEmptyLo;
+            }
+        }
+    }
+
+    // ------------------------------------------------------------------ workspace sizes
+    const int64_t nfilt = std::max<int64_t>(0, P.last_view - P.first_view + 1);
+    P.g4_bytes = align256((uint64_t)nfilt * P.n_psi * cols * 4);
+    P.g2_bytes = align256((uint64_t)nfilt * rows * cols * 4);
+    P.gF_bytes = P.g2_bytes;
+    return KATS_OK;
+}
+
+}  // namespace kats

@@ -1,0 +1,90 @@
+// Host-side float64 plan of the pitch-by-pitch Katsevich reconstruction.
+//
+// Everything that depends only on the scan geometry and the grid of one pitch is
+// computed here once (Sec. II pre-calculating step): kappa-line forward-rebinning
+// rows/weights (eqs. FR, w_k), psi_hat and backward-rebinning indices/weights (eq. BR),
+// PI-line limits of every voxel of the first pitch (pre-calculating step 2), the pitch
+// view window (eq. maxvalue), per-view trigonometry and the Hilbert kernel spectrum
+// (eqs. HF, e4).  The periodicity relations of Sec. II let every later pitch reuse them.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/katsevich.h"
+
+namespace kats {
+
+// One voxel of the PI table, packed for a single 16-byte load in the backprojector.
+// li/lo: PI limits in view units relative to the pitch window start n_lo;
+// nf/nl: first/last view (same origin) with non-zero coverage weight; an empty range
+// (nf > nl) marks a voxel outside the field of view.
+struct PiEntry {
+    float li, lo;
+    int32_t nf, nl;
+};
+static_assert(sizeof(PiEntry) == 16, "PiEntry must be 16 bytes");
+
+// Byte offsets of the sub-tables inside the caller's device table buffer.
+struct TableLayout {
+    uint64_t view = 0;       // float4 [W]   cos(beta), sin(beta), e_m, 0
+    uint64_t fr_row = 0;     // int32  [n_psi][cols]
+    uint64_t fr_w = 0;       // float  [n_psi][cols]
+    uint64_t br_k = 0;       // int32  [rows][cols]
+    uint64_t br_w = 0;       // float  [rows][cols]
+    uint64_t lw = 0;         // float  [rows]
+    uint64_t cos_alpha = 0;  // float  [cols]
+    uint64_t twiddle = 0;    // float2 [fft_len]  exp(-2 pi i k / N)
+    uint64_t hil_im = 0;     // float  [fft_len]  Im(DFT of the Hilbert taps) / N
+    uint64_t pi = 0;         // PiEntry [n_tab][ny][nx]
+    uint64_t total = 0;
+};
+
+struct PlanHost {
+    katsevich_geometry geom{};
+    katsevich_grid grid{};
+    katsevich_options opts{};
+
+    // derived scalars
+    double h = 0, dlam = 0, alpha_m = 0, r_fov = 0, psi_max = 0, dpsi = 0;
+    int n_psi = 0;
+    std::vector<double> alpha, w, psi;
+
+    // kappa rebinning
+    std::vector<int32_t> fr_row;     // [n_psi][cols]
+    std::vector<double> fr_w;
+    std::vector<double> psi_hat;     // [rows][cols]
+    std::vector<int32_t> br_k;
+    std::vector<double> br_w;
+
+    // pitches and PI limits (first pitch)
+    bool commensurate = false;
+    int ns = 0, n_tab = 0, n_pitches = 0;
+    std::vector<double> pi_li, pi_lo;      // global view units, pitch 0
+    std::vector<int32_t> pi_nf, pi_nl;     // global view indices, pitch 0
+    std::vector<uint8_t> fov;
+    int32_t n_lo = 0, n_hi = 0, W = 0;
+    int64_t first_view = 0, last_view = -1, n_vv = 0, n_valid = 0;
+
+    // Hilbert
+    int fft_len = 0;
+    std::vector<double> hil_im;            // [fft_len], already divided by fft_len
+
+    // device image
+    TableLayout layout;
+    std::vector<unsigned char> image;      // table_bytes, copied by katsevich_plan_bind
+    void *d_tables = nullptr;              // caller memory after bind
+
+    // workspace layout (bytes)
+    uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0;
+};
+
+// Build the plan; returns a KATS_* status and fills err on failure.
+int build_plan(const katsevich_geometry &g, const katsevich_grid &grid,
+               const katsevich_options &opts, PlanHost &P, std::string &err);
+
+// Validity of voxel (iz, iy, ix) (integer decision taken from the float64 tables).
+bool voxel_valid(const PlanHost &P, int iz, int iy, int ix);
+
+}  // namespace kats

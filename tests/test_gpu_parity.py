@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+float32 inputs.  Bar (floating point): relative L2 <= 1e-5 and max |error| <= 1e-4 of the
+phantom peak over valid voxels; invalid voxels exactly 0.  Integer tables are compared bit
+for bit in test_plan_host.py."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs, phantom
+
+torch = pytest.importorskip("torch")
+K = pytest.importorskip("paper_2201_02309_amd")
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+MAX_ABS_OF_PEAK = 1e-4
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _grid_points(gr):
+    x = gr["x_first"] + np.arange(gr["nx"]) * gr["dx"]
+    y = gr["y_first"] + np.arange(gr["ny"]) * gr["dy"]
+    z = gr["z_first"] + np.arange(gr["nz"]) * gr["dz"]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return np.stack([X, Y, Z], -1)
+
+
+def _report(name, got, ref, valid, peak):
+    d = (got - ref)[valid]
+    rel = float(np.linalg.norm(d) / max(np.linalg.norm(ref[valid]), 1e-30))
+    mx = float(np.abs(d).max()) if d.size else 0.0
+    print(f"[parity] {name}: rel-L2 {rel:.3e}  max-abs {mx:.3e}  peak {peak:.3f}  "
+          f"valid {int(valid.sum())}", flush=True)
+    return rel, mx
+
+
+class _Case:
+    def __init__(self, wl, n_psi=0):
+        self.wl = wl
+        self.geom, self.grid = wl.geom.as_dict(), wl.grid.as_dict()
+        self.scan = O.Scan(self.geom, n_psi)
+        self.ph = phantom.make_phantom(wl.phantom, self.grid, wl.seed)
+        self.sino = phantom.project(self.ph, self.geom).astype(np.float32)
+        self.tab = O.pitch_tables(self.scan, self.grid)
+        self.ftab = O.FilterTables(self.scan)
+        self._ref = None
+        self.peak = float(phantom.density(self.ph, _grid_points(self.grid)).max())
+
+    @property
+    def ref(self):
+        if self._ref is None:
+            self._ref = O.recon(self.scan, self.grid, self.sino, tables=self.tab, ftables=self.ftab)
+        return self._ref
+
+
+@pytest.fixture(scope="module")
+def case1():
+    return _Case(configs.config1())
+
+
+@pytest.fixture(scope="module")
+def plan1(case1):
+    _dev()
+    return K.Plan(case1.geom, case1.grid, device=0)
+
+
+def test_filter_stage_parity(case1, plan1):
+    dev = _dev()
+    a, b = plan1.info["first_view"], plan1.info["last_view"]
+    print(f"[case] config1 filter views {a}..{b}", flush=True)
+    gF = K.filter_views(plan1, torch.from_numpy(case1.sino).to(dev)).cpu().numpy()
+    ref = O.filter_views(case1.scan, case1.sino[a - 1:b + 2], case1.ftab)[1:-1]
+    rel = np.linalg.norm(gF - ref) / np.linalg.norm(ref)
+    mx = np.abs(gF - ref).max() / np.abs(ref).max()
+    print(f"[parity] filter stage: rel-L2 {rel:.3e} max-abs/max {mx:.3e}", flush=True)
+    assert rel <= REL_L2 and mx <= 1e-5
+
+
+def test_backprojection_stage_parity(case1, plan1):
+    """The GPU backprojector fed the oracle's g^F (rounded to float32) against the oracle
+    backprojection of the same float32 g^F."""
+    dev = _dev()
+    a, b = plan1.info["first_view"], plan1.info["last_view"]
+    gF64 = O.filter_views(case1.scan, case1.sino[a - 1:b + 2], case1.ftab)[1:-1]
+    gF32 = gF64.astype(np.float32)
+    vol = K.backproject(plan1, torch.from_numpy(gF32).to(dev)).cpu().numpy()
+    full = np.zeros((case1.scan.N, case1.scan.rows, case1.scan.cols), np.float32)
+    full[a:b + 1] = gF32
+    ref = np.zeros_like(vol, dtype=np.float64)
+    tab, gr, scan = case1.tab, case1.grid, case1.scan
+    x = gr["x_first"] + np.arange(gr["nx"]) * gr["dx"]
+    y = gr["y_first"] + np.arange(gr["ny"]) * gr["dy"]
+    Y2, X2 = np.meshgrid(y, x, indexing="ij")
+    valid = np.zeros(vol.shape, bool)
+    pit = tab["pitches"]
+    for k in range(pit.n_pitches):
+        sl, js = pit.slices(k)
+        s = k * scan.Nv
+        for iz, j in zip(sl, js):
+            nf, nl = tab["nf"][j] + s, tab["nl"][j] + s
+            m = O.valid_mask(scan, nf, nl, tab["fov"][j])
+            valid[iz] = m
+            zj = gr["z_first"] + j * gr["dz"]
+            ref[iz][m] = O.backproject(scan, full, 0, X2[m], Y2[m], np.full(m.sum(), zj),
+                                       tab["li"][j][m] + s, tab["lo"][j][m] + s, nf[m], nl[m],
+                                       lam_shift=2 * math.pi * k)
+    rel, mx = _report("backprojection stage", vol, ref, valid, case1.peak)
+    assert np.all(vol[~valid] == 0)
+    assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * case1.peak
+
+
+def test_recon_parity_config1(case1, plan1):
+    dev = _dev()
+    vol = K.recon(plan1, torch.from_numpy(case1.sino).to(dev)).cpu().numpy()
+    ref, valid = case1.ref
+    assert np.array_equal(valid, plan1.export("valid").astype(bool))
+    rel, mx = _report("recon config1", vol, ref, valid, case1.peak)
+    assert np.all(vol[~valid] == 0)
+    assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * case1.peak
+
+
+@pytest.mark.parametrize("shape", [(13, 11, 29), (9, 17, 5), (1, 1, 3)])
+def test_recon_ragged_grids(shape):
+    """Grids that are not multiples of the 8 x 8 tile or of the slice run, spanning pitch
+    boundaries (12 slices per pitch), down to a single voxel column."""
+    dev = _dev()
+    nx, ny, nz = shape
+    wl = configs.tiny(nxy=16, nz=nz, cols=48, rows=8, views_per_turn=72, turns=5, feed=24.0,
+                      dxy=2.0, slices_per_pitch=12)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    gr.update(nx=nx, ny=ny, x_first=-0.5 * (nx - 1) * 2.0 + 0.3, y_first=-0.5 * (ny - 1) * 2.0 - 0.7)
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    sino = phantom.project(ph, geom).astype(np.float32)
+    scan = O.Scan(geom)
+    ref, valid = O.recon(scan, gr, sino)
+    plan = K.Plan(geom, gr, device=0)
+    vol = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
+    peak = max(float(phantom.density(ph, _grid_points(gr)).max()), 0.1)
+    print(f"[case] ragged {shape}", flush=True)
+    rel, mx = _report(f"ragged {shape}", vol, ref, valid, peak)
+    assert np.all(vol[~valid] == 0)
+    if valid.any():
+        assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
+
+
+def test_turn_shift_gives_pitch_shift_bit_exact():
+    """Sinogram shifted by one turn (views_per_turn views) -> volume shifted by one pitch,
+    bit for bit: every pitch uses identical pitch-relative geometry and no atomics."""
+    dev = _dev()
+    wl = configs.tiny(nxy=24, nz=36, cols=48, rows=8, views_per_turn=72, turns=6, feed=24.0,
+                      dxy=2.0, slices_per_pitch=12)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    sino = phantom.project(ph, geom).astype(np.float32)
+    sh = np.zeros_like(sino)
+    sh[72:] = sino[:-72]
+    plan = K.Plan(geom, gr, device=0)
+    v0 = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
+    v1 = K.recon(plan, torch.from_numpy(sh).to(dev)).cpu().numpy()
+    valid = plan.export("valid").astype(bool)
+    both = valid[:-12] & valid[12:]
+    assert both.any()
+    assert np.array_equal(v1[12:][both], v0[:-12][both])
+
+
+def test_recon_is_deterministic(case1, plan1):
+    dev = _dev()
+    s = torch.from_numpy(case1.sino).to(dev)
+    a = K.recon(plan1, s).cpu().numpy()
+    b = K.recon(plan1, s).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_wrong_shapes_are_rejected(case1, plan1):
+    dev = _dev()
+    with pytest.raises(K.KatsevichError):
+        K.recon(plan1, torch.zeros((3, 4, 5), device=dev))
+    with pytest.raises(K.KatsevichError):
+        K.recon(plan1, torch.zeros((case1.scan.N, case1.scan.rows, case1.scan.cols),
+                                   dtype=torch.float64, device=dev))
+
+
+# ------------------------------------------------------------------ clinical config (sampled)
+def test_clinical_config_sampled_parity():
+    """512^2 x 128 clinical workload at full size, in the launch configuration the
+    benchmark times: the GPU volume at 300 random voxels (plus 24 near the z ends and the
+    FOV edge) against the oracle computed voxel by voxel from the same float32 sinogram."""
+    dev = _dev()
+    from synth import gpu_projector
+    wl = configs.config2()
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    print("[case] config2 sampled parity", flush=True)
+    plan = K.Plan(geom, gr, device=0)
+    a, b = plan.info["first_view"], plan.info["last_view"]
+    sino_d = torch.zeros((geom["n_views"], geom["det_rows"], geom["det_cols"]),
+                         dtype=torch.float32, device=dev)
+    gpu_projector.project(ph, geom, views=np.arange(a - 1, b + 2), out=sino_d[a - 1:b + 2])
+    # the GPU projector against the closed form on the host, on a few views
+    chk = np.array([a - 1, (a + b) // 2, b + 1])
+    host = phantom.project(ph, geom, views=chk)
+    got = sino_d[torch.from_numpy(chk).to(dev)].cpu().numpy()
+    assert np.abs(got - host).max() <= 1e-5 * np.abs(host).max()
+    vol = K.recon(plan, sino_d).cpu().numpy()
+    torch.cuda.synchronize()
+    sino = sino_d[a - 1:b + 2].cpu().numpy()
+    del sino_d
+    scan = O.Scan(geom)
+    rng = np.random.default_rng(11)
+    n = 300
+    iz = np.concatenate([rng.integers(0, gr["nz"], n), [0, 1, 76, 77, 126, 127] * 4])
+    iy = np.concatenate([rng.integers(0, gr["ny"], n), rng.integers(0, gr["ny"], 24)])
+    ix = np.concatenate([rng.integers(0, gr["nx"], n), np.tile([0, 511, 3, 508], 6)])
+    valid = plan.export("valid").astype(bool)[iz, iy, ix]
+    pit = O.Pitches(scan, gr)
+    k, j = iz // pit.ns, iz % pit.ns
+    x = gr["x_first"] + ix * gr["dx"]
+    y = gr["y_first"] + iy * gr["dy"]
+    zj = gr["z_first"] + j * gr["dz"]
+    Li, Lo = O.pi_line(scan, x, y, zj)
+    li, lo, nf, nl = O.pi_view_bounds(scan, Li, Lo)
+    ref = np.zeros(len(iz))
+    prog = lambda i, n: print(f"[oracle] filtering view {i} of {n}", flush=True)
+    gF = O.filter_views(scan, sino, O.FilterTables(scan), progress=prog)   # views a-1 .. b+1
+    print("[oracle] backprojecting sampled voxels", flush=True)
+    for kk in np.unique(k):
+        m = (k == kk) & valid
+        s = kk * scan.Nv
+        ref[m] = O.backproject(scan, gF, a - 1, x[m], y[m], zj[m], li[m] + s, lo[m] + s,
+                               nf[m] + s, nl[m] + s, lam_shift=2 * math.pi * kk)
+    got = vol[iz, iy, ix]
+    coarse = dict(gr, nx=128, ny=128, nz=32, dx=4 * gr["dx"], dy=4 * gr["dy"], dz=4 * gr["dz"])
+    peak = float(phantom.density(ph, _grid_points(coarse)).max())
+    d = (got - ref)[valid]
+    rel = float(np.linalg.norm(d) / np.linalg.norm(ref[valid]))
+    print(f"[parity] config2 sampled: rel-L2 {rel:.3e} max-abs {np.abs(d).max():.3e} "
+          f"({int(valid.sum())} valid of {len(iz)})", flush=True)
+    assert np.all(got[~valid] == 0)
+    assert rel <= REL_L2 and np.abs(d).max() <= MAX_ABS_OF_PEAK * peak
+
+
+# ------------------------------------------------------------------ adjoint
+@pytest.fixture(scope="module")
+def small_adj():
+    wl = configs.tiny(nxy=12, nz=20, cols=40, rows=8, views_per_turn=60, turns=4, feed=24.0,
+                      dxy=2.5, slices_per_pitch=8)
+    return wl.geom.as_dict(), wl.grid.as_dict()
+
+
+def test_adjoint_dot_product(small_adj):
+    dev = _dev()
+    geom, gr = small_adj
+    plan = K.Plan(geom, gr, device=0)
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(rng.normal(size=(geom["n_views"], geom["det_rows"], geom["det_cols"]))
+                         .astype(np.float32)).to(dev)
+    y = torch.from_numpy(rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)).to(dev)
+    Ax = K.recon(plan, x).double()
+    ATy = K.recon_backward(plan, y).double()
+    lhs = float((Ax * y.double()).sum())
+    rhs = float((x.double() * ATy).sum())
+    rel = abs(lhs - rhs) / (float(Ax.norm()) * float(y.double().norm()))
+    print(f"[parity] adjoint dot product: {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
+def test_adjoint_matches_oracle_transpose(small_adj):
+    dev = _dev()
+    geom, gr = small_adj
+    plan = K.Plan(geom, gr, device=0)
+    rng = np.random.default_rng(6)
+    fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
+    got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev)).cpu().numpy()
+    ref = O.recon_T(O.Scan(geom), gr, fbar.astype(np.float64))
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"[parity] adjoint vs oracle: rel-L2 {rel:.3e}", flush=True)
+    assert rel <= REL_L2
+
+
+def test_autograd_function_gradient(small_adj):
+    dev = _dev()
+    geom, gr = small_adj
+    plan = K.Plan(geom, gr, device=0)
+    rng = np.random.default_rng(7)
+    s = torch.from_numpy(rng.normal(size=(2, geom["n_views"], geom["det_rows"], geom["det_cols"]))
+                         .astype(np.float32)).to(dev).requires_grad_(True)
+    target = torch.from_numpy(rng.normal(size=(2, gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)).to(dev)
+    out = K.KatsevichFn.apply(s, plan)
+    loss = 0.5 * ((out - target) ** 2).sum()
+    loss.backward()
+    for bidx in range(2):
+        expect = K.recon_backward(plan, (out[bidx] - target[bidx]).detach().contiguous())
+        assert torch.allclose(s.grad[bidx], expect, rtol=0, atol=1e-6 * float(expect.abs().max()))

@@ -1,0 +1,159 @@
+"""Host-side tests of the C-ABI library: symbols, validation errors, and the float64 plan
+tables against the oracle (integer tables bit for bit).  No GPU needed: planning runs on
+the host and katsevich_plan_export copies host tables."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs
+
+pk = pytest.importorskip("paper_2201_02309_amd")
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "katsevich.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(katsevich_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pk.load_library()
+    names = _declared()
+    assert "katsevich_recon" in names and "katsevich_recon_backward" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", pk.katsevich.LIB_PATH],
+                         capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (katsevich_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        getattr(lib, n)
+
+
+def test_binding_names_match_header():
+    assert sorted(pk.katsevich.EXPORTED) == _declared()
+
+
+def _plan(wl, **kw):
+    return pk.Plan(wl.geom.as_dict(), wl.grid.as_dict(), bind=False, **kw)
+
+
+def test_rejects_detector_not_covering_td_window():
+    wl = configs.config1()
+    g = wl.geom.as_dict()
+    g["dw"] *= 0.8            # rows cover only 88 % of the TD window
+    with pytest.raises(pk.KatsevichError) as e:
+        pk.Plan(g, wl.grid.as_dict(), bind=False)
+    assert e.value.status == -2 and "Tam-Danielsson" in str(e.value)
+
+
+@pytest.mark.parametrize("field,value", [("views_per_turn", 3), ("n_views", 2), ("R", -1.0),
+                                         ("det_rows", 1), ("dalpha", 0.0), ("dalpha", 0.01)])
+def test_rejects_invalid_geometry(field, value):
+    wl = configs.config1()
+    g = wl.geom.as_dict()
+    g[field] = value
+    with pytest.raises(pk.KatsevichError) as e:
+        pk.Plan(g, wl.grid.as_dict(), bind=False)
+    assert e.value.status == -2
+
+
+def test_rejects_invalid_grid():
+    wl = configs.config1()
+    gr = wl.grid.as_dict()
+    gr["dz"] = 0.0
+    with pytest.raises(pk.KatsevichError):
+        pk.Plan(wl.geom.as_dict(), gr, bind=False)
+
+
+def test_compute_on_unbound_plan_is_an_error():
+    import ctypes
+    wl = configs.tiny()
+    p = _plan(wl)
+    dummy = ctypes.c_void_p(256)     # never dereferenced: rejected before any launch
+    st = p._lib.katsevich_recon(p.handle, dummy, dummy, dummy, ctypes.c_uint64(1 << 30), None)
+    assert st == -5
+    assert b"not bound" in p._lib.katsevich_last_error()
+
+
+def _compare_tables(wl, n_sample=None, seed=0):
+    scan = O.Scan(wl.geom.as_dict(), wl.n_psi)
+    gr = wl.grid.as_dict()
+    p = _plan(wl, n_psi=wl.n_psi)
+    r0, t = O.forward_rebin_table(scan)
+    assert np.array_equal(r0, p.export("fr_row"))
+    assert np.abs(t - p.export("fr_weight")).max() < 1e-12
+    k0, tb = O.backward_rebin_table(scan)
+    assert np.array_equal(k0, p.export("br_kappa"))
+    assert np.abs(tb - p.export("br_weight")).max() < 1e-11
+    assert np.abs(O.psi_hat(scan) - p.export("psi_hat")).max() < 1e-12
+    nf, nl = p.export("pi_nfirst"), p.export("pi_nlast")
+    li, lo, fov = p.export("pi_li"), p.export("pi_lo"), p.export("fov")
+    if n_sample is None:
+        tab = O.pitch_tables(scan, gr)
+        ref = (tab["li"], tab["lo"], tab["nf"], tab["nl"], tab["fov"])
+        got = (li, lo, nf, nl, fov.astype(bool))
+    else:
+        rng = np.random.default_rng(seed)
+        j = rng.integers(0, nf.shape[0], n_sample)
+        iy = rng.integers(0, nf.shape[1], n_sample)
+        ix = rng.integers(0, nf.shape[2], n_sample)
+        x = gr["x_first"] + ix * gr["dx"]
+        y = gr["y_first"] + iy * gr["dy"]
+        z = gr["z_first"] + j * gr["dz"]
+        Li, Lo = O.pi_line(scan, x, y, z)
+        vi, vo, onf, onl = O.pi_view_bounds(scan, Li, Lo)
+        ref = (vi, vo, onf, onl, O.in_fov(scan, x, y))
+        got = (li[j, iy, ix], lo[j, iy, ix], nf[j, iy, ix], nl[j, iy, ix], fov[j, iy, ix].astype(bool))
+    assert np.abs(ref[0] - got[0]).max() < 1e-9
+    assert np.abs(ref[1] - got[1]).max() < 1e-9
+    # integer decisions: report entries within 1e-9 of a floor boundary (expected none)
+    near = np.abs((ref[0] - 0.5) - np.round(ref[0] - 0.5)) < 1e-9
+    assert not near.any(), f"{near.sum()} PI limits within 1e-9 of a view boundary"
+    assert np.array_equal(ref[2], got[2]) and np.array_equal(ref[3], got[3])
+    assert np.array_equal(ref[4], got[4])
+    return p, scan
+
+
+def test_tables_bit_exact_parity_config():
+    wl = configs.config1()
+    p, scan = _compare_tables(wl)
+    gr = wl.grid.as_dict()
+    tab = O.pitch_tables(scan, gr)
+    assert p.info["window_lo"] == tab["n_lo"]
+    assert p.info["window_views"] == tab["n_hi"] - tab["n_lo"] + 1
+    assert p.info["n_vv"] == O.n_voxel_views(scan, gr, tab)
+    # validity mask of the whole grid
+    f_valid = np.zeros((gr["nz"], gr["ny"], gr["nx"]), bool)
+    pit = tab["pitches"]
+    for k in range(pit.n_pitches):
+        sl, js = pit.slices(k)
+        s = k * scan.Nv
+        f_valid[sl] = O.valid_mask(scan, tab["nf"][js] + s, tab["nl"][js] + s, tab["fov"][js])
+    assert np.array_equal(p.export("valid").astype(bool), f_valid)
+
+
+def test_tables_bit_exact_wide_fan_sparse_config():
+    """Sparse-detector geometry: w_kappa turns over inside the psi range."""
+    wl = configs.config3()
+    _compare_tables(wl, n_sample=20000)
+
+
+def test_tables_bit_exact_clinical_config_sampled():
+    wl = configs.config2()
+    p, _ = _compare_tables(wl, n_sample=20000, seed=3)
+    assert p.info["n_pitches"] == 2 and p.info["slices_per_pitch"] == 77
+    assert p.info["commensurate"] == 1
+
+
+def test_non_commensurate_grid_is_one_pitch():
+    wl = configs.tiny(nxy=12, nz=10, cols=40, rows=8, views_per_turn=60, turns=3)
+    gr = wl.grid.as_dict()
+    gr["dz"] = 1.7                    # 24 / 1.7 is not an integer
+    p = pk.Plan(wl.geom.as_dict(), gr, bind=False)
+    assert p.info["commensurate"] == 0 and p.info["n_pitches"] == 1
+    assert p.info["slices_per_pitch"] == 10
