@@ -111,7 +111,7 @@ def main():
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
     sino = gpu_projector.project(ph, geom, device=dev)          # whole scan, resident in HBM
     n_filt = plan.n_filtered
-    gF = torch.empty((n_filt, geom["det_rows"], geom["det_cols"]), dtype=torch.float32, device=dev)
+    gF = torch.empty(K.katsevich.filtered_shape(plan), dtype=torch.float32, device=dev)
     vol = torch.empty((gr["nz"], gr["ny"], gr["nx"]), dtype=torch.float32, device=dev)
     ws = plan.workspace()
     print(f"[bench] plan {t_plan:.2f} s, tables {info['table_bytes'] / 2**20:.0f} MiB, "

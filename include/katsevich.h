@@ -148,8 +148,11 @@ int katsevich_recon(katsevich_plan_t plan, const float *d_sino, float *d_vol,
                     void *d_ws, uint64_t ws_bytes, void *stream);
 
 /* Filtering stage alone (eqs. Deriv, LW, FR, HF, BR, PW): d_sino -> d_gF float32
- * [last_view-first_view+1][rows][cols] holding g^F of views first_view..last_view.
+ * [last_view-first_view+1][rows+2*KATS_GF_PAD][cols+2*KATS_GF_PAD] (filtered_bytes)
+ * holding g^F of views first_view..last_view with a zero border of KATS_GF_PAD cells
+ * (element [v][r+KATS_GF_PAD][c+KATS_GF_PAD] is detector cell (r, c)).
  * d_ws: at least workspace_bytes_filter.  Asynchronous on stream. */
+#define KATS_GF_PAD 2
 int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF,
                      void *d_ws, uint64_t ws_bytes, void *stream);
 

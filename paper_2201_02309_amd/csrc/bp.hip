@@ -4,20 +4,14 @@
 // v* = R - x cos(b) - y sin(b), alpha* = atan(u / v*), u = -x sin(b) + y cos(b),
 // w* = D cos(alpha*) / v* (z - z0 - P lambda / 2 pi) = D (z - z0 - P lambda / 2 pi) / sqrt(u^2+v*^2),
 // with b = lambda + lambda0 and c_n the overlap of view cell [n-1/2, n+1/2] with the PI
-// interval [l_i, l_o] (view units).
+// interval [l_i, l_o] (view units); c_n differs from 0 and 1 only at the first and last
+// view of the interval.
 //
 // Every pitch k reuses the first pitch's tables (Sec. II periodicity): slice j of pitch k
 // sees view n = n_lo + k Nv + m exactly as slice j of pitch 0 sees view n_lo + m, so the
-// per-view table (cos b, sin b, e_m = z_first - z0 - h lambda_{n_lo+m}) and the PI table
-// (l_i, l_o, n_first, n_last relative to n_lo) are indexed by the pitch-relative view m
-// and slice j only.  The geometry is therefore bit-identical for every pitch.
-//
-// Thread layout: one wave (64 lanes) = an 8 x 8 (x, y) tile; each lane owns a run of
-// KZ consecutive slices of one pitch and keeps their accumulators in registers.  The
-// wave walks the hull of its lanes' PI windows (a wave-uniform loop, view table read
-// through scalar loads); alpha*, 1/v* and 1/rho are computed once per (lane, view) and
-// shared by the KZ slices, whose detector rows advance by dz D / rho per slice.  Each
-// voxel is written exactly once, no atomics.
+// per-view table (cos b, sin b, e_m = z_first - z0 - h lambda_{n_lo+m}), the PI table
+// (l_i, l_o, n_first, n_last relative to n_lo) and the footprint boxes are indexed by the
+// pitch-relative view m and slice j only: the geometry is bit-identical for every pitch.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -28,9 +22,6 @@ namespace kats {
 
 namespace {
 
-constexpr int kTile = 8;          // 8 x 8 lanes per wave
-constexpr int kKZ = 8;            // slices per lane
-
 __device__ inline int wave_min(int v) {
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
     return v;
@@ -40,84 +31,247 @@ __device__ inline int wave_max(int v) {
     return v;
 }
 
-// detector sample with zero outside [0, rows) x [0, cols)
-__device__ inline float tap(const float *__restrict__ img, int r, int c, int rows, int cols) {
-    return ((unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols) ? img[r * cols + c] : 0.0f;
+__device__ inline float med3(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+
+// ---------------------------------------------------------------------------------
+// Forward backprojection.  Workgroup = 256 lanes = a 16 x 16 (x, y) tile (4 waves of
+// 16 x 4) x a run of KZ consecutive slices of one pitch; every lane keeps KZ accumulators.
+// The workgroup walks the hull of its voxels' PI windows view by view.  For each view the
+// plan gives the tile's detector footprint box (float64 bound); the box of view m+1 is
+// loaded from HBM into registers while view m is backprojected from LDS, then stored into
+// the other LDS buffer (one barrier per view).  Per (lane, view): v*, 1/v*, 1/rho and the
+// column coordinate (atan); per (lane, view, slice): the row coordinate (one FMA: rows
+// advance by dz D / (rho dw) per slice), two ds_read2 of the 2 x 2 taps, three lerps and
+// one FMA into the accumulator.  Before the view loop every wave classifies each view of
+// the hull into a 32-bit word (bit j: some voxel of slice j is active; bit 16+j: every
+// valid voxel of slice j has c_n = 1): inactive slices are skipped by a wave-uniform
+// branch and fully covered ones skip the coverage arithmetic.  Boxes larger than the LDS
+// tile read the same taps from the zero-padded g^F in HBM instead.
+// ---------------------------------------------------------------------------------
+constexpr int kT = kBpTile;       // 16
+constexpr int kNT = kT * kT;      // 256 lanes
+constexpr int kLP = 64;           // LDS tile row pitch (floats) = max box columns
+constexpr int kLR = 32;           // max box rows
+constexpr int kLMax = kLP * kLR;  // 2048 floats per buffer
+constexpr int kPF = (kLMax + kNT - 1) / kNT;
+constexpr int kHull = 2048;       // max views of a workgroup hull with per-view group words
+constexpr int kKG = 4;            // slices per branch group
+
+// The scalars the backprojector needs (a slim kernel argument keeps SGPR pressure low).
+struct BpArgs {
+    const float4 *view;
+    const PiEntry *pi;
+    const BpBox *boxes;
+    long long n_views, first_view;
+    float R, inv_dalpha, col_c, q_scale, row_c, dz, x_first, y_first, dx, dy, scale;
+    int nx, ny, nz, ns, Nv, n_lo, W, runs, tiles_x, tiles_y, rows, cols;
+};
+
+__device__ inline float lerp_bilinear(const float *t, int pitch_f, float tc, float tr) {
+    const float v00 = t[0], v01 = t[1], v10 = t[pitch_f], v11 = t[pitch_f + 1];
+    const float top = fmaf(tc, v01 - v00, v00);
+    const float bot = fmaf(tc, v11 - v10, v10);
+    return fmaf(tr, bot - top, top);
 }
 
 template <int KZ>
-__global__ __launch_bounds__(64) void k_backproject(KParams p, const float *__restrict__ gF,
-                                                    float *__restrict__ vol, int runs_per_pitch) {
-    const int lane = threadIdx.x;
-    const int ix = blockIdx.x * kTile + (lane & (kTile - 1));
-    const int iy = blockIdx.y * kTile + (lane >> 3);
-    const int pitch = blockIdx.z / runs_per_pitch;
-    const int j0 = (blockIdx.z % runs_per_pitch) * KZ;
+__global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restrict__ gF,
+                                                float *__restrict__ vol) {
+    static_assert(KZ % kKG == 0 && KZ / kKG <= 4, "groups use 4-bit masks");
+    constexpr int NG = KZ / kKG;
+    __shared__ float lds[2][kLMax];
+    __shared__ unsigned char words[4][kHull];   // per wave and view: active groups | full groups << 4
+    __shared__ int red[8];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int ix = blockIdx.x * kT + (tid & (kT - 1));
+    const int iy = blockIdx.y * kT + (tid >> 4);
+    const int pitch = blockIdx.z / p.runs;
+    const int run = blockIdx.z % p.runs;
+    const int j0 = run * KZ;
     const int slices = min(p.ns, p.nz - pitch * p.ns);
     const int nrun = min(KZ, slices - j0);
-    if (nrun <= 0) return;                                   // whole wave: uniform
+    if (nrun <= 0) return;                                   // uniform over the workgroup
     const bool inxy = ix < p.nx && iy < p.ny;
     const long long base = (long long)p.n_lo + (long long)pitch * p.Nv;   // view of m = 0
 
     float A[KZ], B[KZ], acc[KZ];
     unsigned valid = 0;
-    int mlo = INT_MAX, mhi = INT_MIN;
+    int wlo = INT_MAX, whi = INT_MIN;
+    int g_alo[NG], g_ahi[NG], g_flo[NG], g_fhi[NG];
 #pragma unroll
-    for (int jj = 0; jj < KZ; ++jj) {
-        A[jj] = 3.0e38f;
-        B[jj] = -3.0e38f;
-        acc[jj] = 0.0f;
-        if (inxy && jj < nrun) {
-            const PiEntry e = p.pi[((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix];
-            const long long nf = base + e.nf, nl = base + e.nl;
-            if (e.nf <= e.nl && nf - 1 >= 0 && nl + 1 <= p.n_views - 1) {
-                A[jj] = e.li - 0.5f;           // c_n = clamp(min(m - A, B - m), 0, 1)
-                B[jj] = e.lo + 0.5f;
-                valid |= 1u << jj;
-                mlo = min(mlo, e.nf);
-                mhi = max(mhi, e.nl);
+    for (int g = 0; g < NG; ++g) {
+        int alo = INT_MAX, ahi = INT_MIN, flo = INT_MIN, fhi = INT_MAX;
+#pragma unroll
+        for (int s = 0; s < kKG; ++s) {
+            const int jj = g * kKG + s;
+            A[jj] = 3.0e38f;
+            B[jj] = -3.0e38f;
+            acc[jj] = 0.0f;
+            if (inxy && jj < nrun) {
+                const PiEntry e = p.pi[((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix];
+                const long long nf = base + e.nf, nl = base + e.nl;
+                if (e.nf <= e.nl && nf - 1 >= 0 && nl + 1 <= p.n_views - 1) {
+                    A[jj] = e.li - 0.5f;      // c_n = clamp(min(m - A, B - m), 0, 1)
+                    B[jj] = e.lo + 0.5f;
+                    valid |= 1u << jj;
+                    alo = min(alo, e.nf);
+                    ahi = max(ahi, e.nl);
+                    // views with c_n = 1 for certain (one view of margin against rounding)
+                    flo = max(flo, (int)ceilf(A[jj] + 1.0f) + 1);
+                    fhi = min(fhi, (int)floorf(B[jj] - 1.0f) - 1);
+                }
             }
         }
+        // a group is active at m if one of its voxels is; full if every valid voxel of the
+        // group has c_n = 1 at m
+        g_alo[g] = wave_min(alo);
+        g_ahi[g] = wave_max(ahi);
+        g_flo[g] = wave_max(flo);
+        g_fhi[g] = wave_min(fhi);
+        wlo = min(wlo, g_alo[g]);
+        whi = max(whi, g_ahi[g]);
     }
-    mlo = __builtin_amdgcn_readfirstlane(wave_min(mlo));
-    mhi = __builtin_amdgcn_readfirstlane(wave_max(mhi));
+    if (lane == 0) {
+        red[wave] = wlo;
+        red[4 + wave] = whi;
+    }
+    __syncthreads();
+    const int mlo = min(min(red[0], red[1]), min(red[2], red[3]));
+    const int mhi = max(max(red[4], red[5]), max(red[6], red[7]));
+    // Per-view group classification of this wave.  A hull longer than kHull views
+    // takes the coverage path for every group at every view, which is exact.
+    const bool use_words = mhi - mlo + 1 <= kHull;
+    if (use_words) {
+        for (int w = lane; w <= mhi - mlo; w += 64) {
+            const int m = mlo + w;
+            unsigned word = 0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (m >= g_alo[g] && m <= g_ahi[g]) word |= 1u << g;
+                if (m >= g_flo[g] && m <= g_fhi[g]) word |= 1u << (4 + g);
+            }
+            words[wave][w] = (unsigned char)word;
+        }
+    }
 
     const float x = fmaf((float)ix, p.dx, p.x_first);
     const float y = fmaf((float)iy, p.dy, p.y_first);
     const float zoff = (float)j0 * p.dz;
-    const size_t rc = (size_t)p.rows * p.cols;
+    const int cpitch = p.cols + 2 * kPad;
+    const size_t vstride = (size_t)(p.rows + 2 * kPad) * cpitch;
+    const BpBox *boxes = p.boxes + ((size_t)(run * p.tiles_y + blockIdx.y) * p.tiles_x +
+                                    blockIdx.x) * p.W;
+    // g^F of pitch-relative view 0; element (0, 0) of a view is detector cell (-kPad, -kPad)
+    const float *gF0 = gF + (size_t)(base - p.first_view) * vstride;
+    auto fits = [](const BpBox &b) { return b.nr <= kLR && b.nc <= kLP; };
+
+    if (mlo <= mhi) {
+        const BpBox b = boxes[mlo];
+        if (fits(b)) {
+            const float *src = gF0 + (size_t)mlo * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad);
+            const int n_el = b.nr * b.nc;
+            const float inv_nc = 1.0f / (float)b.nc;
+            for (int e = tid; e < n_el; e += kNT) {
+                const int r = (int)(((float)e + 0.5f) * inv_nc);
+                const int c = e - r * b.nc;
+                lds[0][r * kLP + c] = src[r * cpitch + c];
+            }
+        }
+    }
+    __syncthreads();
     for (int m = mlo; m <= mhi; ++m) {
+        const int buf = (m - mlo) & 1;
+        const BpBox b = boxes[m];
+        // prefetch the next view's box into registers
+        float pf[kPF];
+        BpBox bn = b;
+        bool next_fits = false;
+        int n_next = 0;
+        float inv_nc_next = 1.0f;
+        if (m < mhi) {
+            bn = boxes[m + 1];
+            next_fits = fits(bn);
+            if (next_fits) {
+                n_next = bn.nr * bn.nc;
+                inv_nc_next = 1.0f / (float)bn.nc;
+                const float *src = gF0 + (size_t)(m + 1) * vstride + (bn.r0 + kPad) * cpitch + (bn.c0 + kPad);
+#pragma unroll
+                for (int k = 0; k < kPF; ++k) {
+                    const int e = tid + k * kNT;
+                    if (e < n_next) {
+                        const int r = (int)(((float)e + 0.5f) * inv_nc_next);
+                        const int c = e - r * bn.nc;
+                        pf[k] = src[r * cpitch + c];
+                    }
+                }
+            }
+        }
+        // per (lane, view) geometry; coordinates relative to the box origin, clamped into
+        // the box (only voxels projecting outside the zero-padded detector are clamped)
         const float4 vt = p.view[m];
         const float u = fmaf(-x, vt.y, y * vt.x);
         const float v = p.R - fmaf(x, vt.x, y * vt.y);
-        const float vinv = 1.0f / v;
-        const float rinv = rsqrtf(fmaf(u, u, v * v));
-        const float cc = fmaf(atan2f(u, v), p.inv_dalpha, p.col_c);
-        const float ccl = fminf(fmaxf(cc, -2.0f), (float)p.cols);
-        const float c0f = floorf(ccl);
-        const float tc = ccl - c0f;
-        const int c0 = (int)c0f;
-        const float q = p.D * rinv * p.inv_dw;               // rows per mm of z
-        const float ez = vt.z + zoff;                        // z - z0 - h lambda at slice j0
-        const float *img = gF + (size_t)(base + m - p.first_view) * rc;
+        const float vinv = __builtin_amdgcn_rcpf(v);
+        const float rinv = __builtin_amdgcn_rsqf(fmaf(u, u, v * v));
+        const float cc = med3(fmaf(atan2f(u, v), p.inv_dalpha, p.col_c - (float)b.c0), 0.0f,
+                              (float)(b.nc - 2));
+        const int c0 = (int)cc;
+        const float tc = cc - (float)c0;
+        const float q = p.q_scale * rinv;                   // detector rows per mm of z
+        const float rb = fmaf(q, vt.z + zoff, p.row_c - (float)b.r0);
+        const float st = q * p.dz;
+        const float rmax = (float)(b.nr - 2);
         const float mf = (float)m;
+        unsigned word = (1u << NG) - 1u;                    // all groups active, none full
+        if (use_words) word = __builtin_amdgcn_readfirstlane(words[wave][m - mlo]);
+        // one group of kKG slices: taps of all its slices first (independent LDS / HBM
+        // loads), then the accumulation with or without the coverage weight
+        auto group = [&](const float *T, int tp, int g) {
+            float val[kKG];
 #pragma unroll
-        for (int jj = 0; jj < KZ; ++jj) {
-            const float rr = fmaf(q, fmaf((float)jj, p.dz, ez), p.row_c);
-            const float rrl = fminf(fmaxf(rr, -2.0f), (float)p.rows);
-            const float r0f = floorf(rrl);
-            const float tr = rrl - r0f;
-            const int r0 = (int)r0f;
-            const float v00 = tap(img, r0, c0, p.rows, p.cols);
-            const float v01 = tap(img, r0, c0 + 1, p.rows, p.cols);
-            const float v10 = tap(img, r0 + 1, c0, p.rows, p.cols);
-            const float v11 = tap(img, r0 + 1, c0 + 1, p.rows, p.cols);
-            const float top = fmaf(tc, v01 - v00, v00);
-            const float bot = fmaf(tc, v11 - v10, v10);
-            const float val = fmaf(tr, bot - top, top);
-            const float cw = fminf(fmaxf(fminf(mf - A[jj], B[jj] - mf), 0.0f), 1.0f);
-            acc[jj] = fmaf(cw * vinv, val, acc[jj]);
+            for (int s = 0; s < kKG; ++s) {
+                const float rr = med3(fmaf((float)(g * kKG + s), st, rb), 0.0f, rmax);
+                const int r0 = (int)rr;               // rr >= 0: truncation = floor
+                val[s] = lerp_bilinear(T + r0 * tp, tp, tc, __builtin_amdgcn_fractf(rr));
+            }
+            if (word & (1u << (4 + g))) {
+#pragma unroll
+                for (int s = 0; s < kKG; ++s) acc[g * kKG + s] = fmaf(vinv, val[s], acc[g * kKG + s]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < kKG; ++s) {
+                    const int jj = g * kKG + s;
+                    const float cw = med3(fminf(mf - A[jj], B[jj] - mf), 0.0f, 1.0f);
+                    acc[jj] = fmaf(cw * vinv, val[s], acc[jj]);
+                }
+            }
+        };
+        if (fits(b)) {
+            const float *T = &lds[buf][c0];
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                if (word & (1u << g)) group(T, kLP, g);
+        } else {
+            const float *T = gF0 + (size_t)m * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad) + c0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                if (word & (1u << g)) group(T, cpitch, g);
         }
+        if (next_fits) {
+            float *Dst = lds[buf ^ 1];
+#pragma unroll
+            for (int k = 0; k < kPF; ++k) {
+                const int e = tid + k * kNT;
+                if (e < n_next) {
+                    const int r = (int)(((float)e + 0.5f) * inv_nc_next);
+                    const int c = e - r * bn.nc;
+                    Dst[r * kLP + c] = pf[k];
+                }
+            }
+        }
+        __syncthreads();
     }
     if (!inxy) return;
     const int iz0 = pitch * p.ns + j0;
@@ -128,6 +282,13 @@ __global__ __launch_bounds__(64) void k_backproject(KParams p, const float *__re
                 ((valid >> jj) & 1u) ? acc[jj] * p.scale : 0.0f;
     }
 }
+
+// ---------------------------------------------------------------------------------
+// Adjoint of the backprojection (the transpose of the operator above, acting on an
+// unpadded g^F cotangent).
+// ---------------------------------------------------------------------------------
+constexpr int kTile = 8;          // 8 x 8 lanes per wave
+constexpr int kKZ = 8;            // slices per lane
 
 // Transpose: gFbar[n] += dlambda/(2 pi) c_n / v*_n * fbar(x) spread over the four bilinear
 // taps (global float atomics; the adjoint's only non-deterministic summation order).
@@ -213,10 +374,37 @@ __global__ __launch_bounds__(64) void k_backproject_T(KParams p, const float *__
 }  // namespace
 
 hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s) {
-    const int ns_eff = k.ns < k.nz ? k.ns : k.nz;
-    const int runs = (ns_eff + kKZ - 1) / kKZ;
-    dim3 grid((k.nx + kTile - 1) / kTile, (k.ny + kTile - 1) / kTile, (unsigned)(k.n_pitches * runs));
-    hipLaunchKernelGGL(k_backproject<kKZ>, grid, dim3(64), 0, s, k, gF, vol, runs);
+    dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
+    BpArgs a;
+    a.view = k.view;
+    a.pi = k.pi;
+    a.boxes = k.boxes;
+    a.n_views = k.n_views;
+    a.first_view = k.first_view;
+    a.R = k.R;
+    a.inv_dalpha = k.inv_dalpha;
+    a.col_c = k.col_c;
+    a.q_scale = k.D * k.inv_dw;
+    a.row_c = k.row_c;
+    a.dz = k.dz;
+    a.x_first = k.x_first;
+    a.y_first = k.y_first;
+    a.dx = k.dx;
+    a.dy = k.dy;
+    a.scale = k.scale;
+    a.nx = k.nx;
+    a.ny = k.ny;
+    a.nz = k.nz;
+    a.ns = k.ns;
+    a.Nv = k.Nv;
+    a.n_lo = k.n_lo;
+    a.W = k.W;
+    a.runs = k.bp_runs;
+    a.tiles_x = k.bp_tiles_x;
+    a.tiles_y = k.bp_tiles_y;
+    a.rows = k.rows;
+    a.cols = k.cols;
+    hipLaunchKernelGGL(k_bp_lds<kBpKZ>, grid, dim3(kNT), 0, s, a, gF, vol);
     return hipGetLastError();
 }
 

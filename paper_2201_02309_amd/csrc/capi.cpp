@@ -2,6 +2,7 @@
 // workspace carving and the launch sequence on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -84,6 +85,10 @@ KParams make_params(const PlanHost &P) {
     k.twiddle = reinterpret_cast<const float2 *>(base + L.twiddle);
     k.hil_im = reinterpret_cast<const float *>(base + L.hil_im);
     k.pi = reinterpret_cast<const PiEntry *>(base + L.pi);
+    k.boxes = reinterpret_cast<const BpBox *>(base + L.boxes);
+    k.bp_tiles_x = P.bp_tiles_x;
+    k.bp_tiles_y = P.bp_tiles_y;
+    k.bp_runs = P.bp_runs;
     return k;
 }
 
@@ -143,7 +148,7 @@ int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
     const kats::PlanHost &P = plan->P;
     katsevich_plan_info i{};
     i.table_bytes = P.layout.total;
-    i.workspace_bytes = P.g4_bytes + P.g2_bytes;
+    i.workspace_bytes = P.g4_bytes + std::max(P.g2_bytes, P.gF_bytes);
     i.filtered_bytes = P.gF_bytes;
     i.workspace_bytes_filter = P.g4_bytes + P.g2_bytes;
     i.first_view = P.first_view;
@@ -253,14 +258,16 @@ int katsevich_recon(katsevich_plan_t plan, const float *d_sino, float *d_vol, vo
     int st = check_compute(plan, d_sino, d_vol, "katsevich_recon");
     if (st) return st;
     const kats::PlanHost &P = plan->P;
-    if (P.g4_bytes + P.g2_bytes > 0 && (!d_ws || ws_bytes < P.g4_bytes + P.g2_bytes))
+    const uint64_t need = P.g4_bytes + std::max(P.g2_bytes, P.gF_bytes);
+    if (need > 0 && (!d_ws || ws_bytes < need))
         return fail(KATS_EWORKSPACE, "katsevich_recon: workspace too small");
     if (d_ws && !aligned256(d_ws)) return fail(KATS_EINVAL, "katsevich_recon: workspace not 256-byte aligned");
     const kats::KParams k = kats::make_params(P);
     hipStream_t s = static_cast<hipStream_t>(stream);
     float *g4 = static_cast<float *>(d_ws);
     float *g2 = reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + P.g4_bytes);
-    // g^F overwrites g2 (consumed by the Hilbert stage before the backward rebinning runs)
+    // the padded g^F overwrites g2 (consumed by the Hilbert stage before the backward
+    // rebinning runs)
     hipError_t e = kats::launch_filter(k, d_sino, g2, g4, g2, s);
     if (e != hipSuccess) return hip_fail(e, "katsevich_recon: filter launch");
     e = kats::launch_backproject(k, g2, d_vol, s);

@@ -34,6 +34,8 @@ struct KParams {
     const float2 *twiddle;
     const float *hil_im;
     const PiEntry *pi;
+    const BpBox *boxes;
+    int bp_tiles_x, bp_tiles_y, bp_runs;
 };
 
 KParams make_params(const PlanHost &P);

@@ -171,6 +171,18 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     if (!(a_last < 0.5 * kPi && -a_first < 0.5 * kPi)) return bad("|alpha| must stay below pi/2");
     P.alpha_m = std::max(std::fabs(a_first), std::fabs(a_last));
     P.r_fov = g.R * std::sin(std::min(-a_first, a_last));
+    {
+        // every lane of a backprojection tile (the grid rounded up to whole tiles) must see
+        // the source in front of it (v* > 0): keep that extent well inside the helix radius
+        const int ex = ((gr.nx + kBpTile - 1) / kBpTile) * kBpTile - 1;
+        const int ey = ((gr.ny + kBpTile - 1) / kBpTile) * kBpTile - 1;
+        const double xs[2] = {gr.x_first, gr.x_first + ex * gr.dx};
+        const double ys[2] = {gr.y_first, gr.y_first + ey * gr.dy};
+        double rmax = 0.0;
+        for (double xv : xs)
+            for (double yv : ys) rmax = std::max(rmax, std::hypot(xv, yv));
+        if (rmax >= 0.9 * g.R) return bad("grid extends beyond 0.9 R from the axis");
+    }
 
     // Tam-Danielsson window of the curved detector: w_top(a) = (D P/2pi R)(pi/2 - a)/cos a,
     // w_bot(a) = -(D P/2pi R)(pi/2 + a)/cos a, must lie inside the row range.
@@ -348,6 +360,11 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     L.twiddle = take((uint64_t)N * 8);
     L.hil_im = take((uint64_t)N * 4);
     L.pi = take((uint64_t)nvox * sizeof(PiEntry));
+    P.bp_tiles_x = (gr.nx + kBpTile - 1) / kBpTile;
+    P.bp_tiles_y = (gr.ny + kBpTile - 1) / kBpTile;
+    P.bp_runs = (P.n_tab + kBpKZ - 1) / kBpKZ;
+    const uint64_t n_boxes = (uint64_t)P.bp_runs * P.bp_tiles_y * P.bp_tiles_x * P.W;
+    L.boxes = take(n_boxes * sizeof(BpBox));
     L.total = off;
     try {
         P.image.assign(L.total, 0);
@@ -406,11 +423,77 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
         }
     }
 
+    // ------------------------------------------------------------------ footprint boxes
+    // Columns: alpha* over a rectangle seen from an outside point is extremal at a corner
+    // (its level sets are rays from the source).  Rows: w* = D dz / rho with rho between the
+    // distance from the source to the rectangle and to its farthest corner, dz between
+    // the run's first and last slice.  One extra cell each side absorbs float32 rounding
+    // in the kernel; the box is clipped to the zero-padded detector.
+    {
+        BpBox *bx = reinterpret_cast<BpBox *>(img + L.boxes);
+        const double col_c = 0.5 * (cols - 1) - g.col_offset;
+        const double row_c = 0.5 * (rows - 1) - g.row_offset;
+        const int tiles = P.bp_runs * P.bp_tiles_y * P.bp_tiles_x;
+        parallel_for(tiles, threads_for(opts), [&](int t) {
+            const int tx = t % P.bp_tiles_x;
+            const int ty = (t / P.bp_tiles_x) % P.bp_tiles_y;
+            const int run = t / (P.bp_tiles_x * P.bp_tiles_y);
+            const double x0 = gr.x_first + (double)tx * kBpTile * gr.dx;
+            const double x1 = gr.x_first + (double)(tx * kBpTile + kBpTile - 1) * gr.dx;
+            const double y0 = gr.y_first + (double)ty * kBpTile * gr.dy;
+            const double y1 = gr.y_first + (double)(ty * kBpTile + kBpTile - 1) * gr.dy;
+            const double zs0 = (double)(run * kBpKZ) * gr.dz;
+            const double zs1 = (double)(run * kBpKZ + kBpKZ - 1) * gr.dz;
+            const double cx[4] = {x0, x1, x0, x1}, cy[4] = {y0, y0, y1, y1};
+            BpBox *out = bx + (size_t)t * P.W;
+            for (int m = 0; m < P.W; ++m) {
+                const double lam = g.lambda_first + (double)(P.n_lo + m) * P.dlam;
+                const double b = lam + g.lambda0;
+                const double cb = std::cos(b), sb = std::sin(b);
+                const double Sx = g.R * cb, Sy = g.R * sb;
+                double amin = 1e300, amax = -1e300, rmax = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    const double u = -cx[k] * sb + cy[k] * cb;
+                    const double v = g.R - cx[k] * cb - cy[k] * sb;
+                    const double a = std::atan2(u, v);
+                    amin = std::min(amin, a);
+                    amax = std::max(amax, a);
+                    rmax = std::max(rmax, std::hypot(cx[k] - Sx, cy[k] - Sy));
+                }
+                const double ddx = std::max({x0 - Sx, 0.0, Sx - x1});
+                const double ddy = std::max({y0 - Sy, 0.0, Sy - y1});
+                const double rmin = std::max(std::hypot(ddx, ddy), 1e-9);
+                const double e = gr.z_first - g.z0 - P.h * lam;
+                const double dz0 = e + zs0, dz1 = e + zs1;
+                const double wlo = g.D * dz0 / (dz0 >= 0 ? rmax : rmin);
+                const double whi = g.D * dz1 / (dz1 >= 0 ? rmin : rmax);
+                auto clip = [](double lo, double hi, int n) {
+                    // cells [lo, hi] clipped to [-kPad, n-1+kPad], at least two cells
+                    double a = std::floor(lo) - 1.0, c = std::floor(hi) + 2.0;
+                    a = std::max(a, (double)-kPad);
+                    c = std::min(c, (double)(n - 1 + kPad));
+                    int ia = (int)std::min(a, 1e6), ic = (int)std::max(c, -1e6);
+                    if (ic - ia < 1) {
+                        if (ia >= n) { ia = n + kPad - 2; ic = n + kPad - 1; }
+                        else { ia = -kPad; ic = -kPad + 1; }
+                    }
+                    return std::make_pair(ia, ic - ia + 1);
+                };
+                const auto rr = clip(wlo / g.dw + row_c, whi / g.dw + row_c, rows);
+                const auto cc = clip(amin / g.dalpha + col_c, amax / g.dalpha + col_c, cols);
+                out[m].r0 = (int16_t)rr.first;
+                out[m].nr = (int16_t)rr.second;
+                out[m].c0 = (int16_t)cc.first;
+                out[m].nc = (int16_t)cc.second;
+            }
+        });
+    }
+
     // ------------------------------------------------------------------ workspace sizes
     const int64_t nfilt = std::max<int64_t>(0, P.last_view - P.first_view + 1);
     P.g4_bytes = align256((uint64_t)nfilt * P.n_psi * cols * 4);
     P.g2_bytes = align256((uint64_t)nfilt * rows * cols * 4);
-    P.gF_bytes = P.g2_bytes;
+    P.gF_bytes = align256((uint64_t)nfilt * (rows + 2 * kPad) * (cols + 2 * kPad) * 4);
     return KATS_OK;
 }
 

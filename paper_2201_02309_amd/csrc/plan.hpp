@@ -26,6 +26,23 @@ struct PiEntry {
 };
 static_assert(sizeof(PiEntry) == 16, "PiEntry must be 16 bytes");
 
+// Backprojection tiling: a workgroup owns a kBpTile x kBpTile (x, y) tile and a run of
+// kBpKZ consecutive slices of one pitch.
+constexpr int kBpTile = 16;
+constexpr int kBpKZ = 16;
+// Rows / columns of zero padding around every filtered view g^F (so that clamped
+// bilinear taps outside the detector read exact zeros).
+constexpr int kPad = 2;
+
+// Detector footprint (absolute row/col origin, may be -kPad, and extent) of one
+// backprojection tile x slice run at one pitch-relative view: every bilinear tap of
+// every voxel of the tile lies inside it (float64 bound plus a one-cell margin),
+// clipped to the zero-padded detector.
+struct BpBox {
+    int16_t r0, nr, c0, nc;
+};
+static_assert(sizeof(BpBox) == 8, "BpBox must be 8 bytes");
+
 // Byte offsets of the sub-tables inside the caller's device table buffer.
 struct TableLayout {
     uint64_t view = 0;       // float4 [W]   cos(beta), sin(beta), e_m, 0
@@ -38,6 +55,7 @@ struct TableLayout {
     uint64_t twiddle = 0;    // float2 [fft_len]  exp(-2 pi i k / N)
     uint64_t hil_im = 0;     // float  [fft_len]  Im(DFT of the Hilbert taps) / N
     uint64_t pi = 0;         // PiEntry [n_tab][ny][nx]
+    uint64_t boxes = 0;      // BpBox   [runs][tiles_y][tiles_x][W]
     uint64_t total = 0;
 };
 
@@ -65,6 +83,7 @@ struct PlanHost {
     std::vector<int32_t> pi_nf, pi_nl;     // global view indices, pitch 0
     std::vector<uint8_t> fov;
     int32_t n_lo = 0, n_hi = 0, W = 0;
+    int bp_tiles_x = 0, bp_tiles_y = 0, bp_runs = 0;
     int64_t first_view = 0, last_view = -1, n_vv = 0, n_valid = 0;
 
     // Hilbert
@@ -77,7 +96,7 @@ struct PlanHost {
     void *d_tables = nullptr;              // caller memory after bind
 
     // workspace layout (bytes)
-    uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0;
+    uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0;   // gF: padded [n][rows+2kPad][cols+2kPad]
 };
 
 // Build the plan; returns a KATS_* status and fills err on failure.

@@ -244,11 +244,20 @@ def recon(plan: Plan, sino, out=None, ws=None):
     return out
 
 
+PAD = 2   # zero border (cells) around every filtered view, see include/katsevich.h
+
+
+def filtered_shape(plan: Plan):
+    """Shape of the g^F buffer: [n_filtered, rows + 2 PAD, cols + 2 PAD]."""
+    return (plan.n_filtered, int(plan.geom["det_rows"]) + 2 * PAD,
+            int(plan.geom["det_cols"]) + 2 * PAD)
+
+
 def filter_views(plan: Plan, sino, out=None, ws=None):
-    """katsevich_filter: sino -> g^F of views first_view..last_view."""
+    """katsevich_filter: sino -> zero-padded g^F of views first_view..last_view."""
     import torch
     _require(sino, _sino_shape(plan), "sino")
-    shape = (plan.n_filtered, int(plan.geom["det_rows"]), int(plan.geom["det_cols"]))
+    shape = filtered_shape(plan)
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=sino.device)
     _require(out, shape, "out")
@@ -261,9 +270,9 @@ def filter_views(plan: Plan, sino, out=None, ws=None):
 
 
 def backproject(plan: Plan, gF, out=None):
-    """katsevich_backproject: g^F (views first_view..last_view) -> vol."""
+    """katsevich_backproject: zero-padded g^F (views first_view..last_view) -> vol."""
     import torch
-    shape = (plan.n_filtered, int(plan.geom["det_rows"]), int(plan.geom["det_cols"]))
+    shape = filtered_shape(plan)
     _require(gF, shape, "gF")
     if out is None:
         out = torch.empty(_vol_shape(plan), dtype=torch.float32, device=gF.device)

@@ -76,7 +76,11 @@ def test_filter_stage_parity(case1, plan1):
     dev = _dev()
     a, b = plan1.info["first_view"], plan1.info["last_view"]
     print(f"[case] config1 filter views {a}..{b}", flush=True)
-    gF = K.filter_views(plan1, torch.from_numpy(case1.sino).to(dev)).cpu().numpy()
+    gFp = K.filter_views(plan1, torch.from_numpy(case1.sino).to(dev)).cpu().numpy()
+    P = K.katsevich.PAD
+    assert np.all(gFp[:, :P] == 0) and np.all(gFp[:, -P:] == 0)
+    assert np.all(gFp[:, :, :P] == 0) and np.all(gFp[:, :, -P:] == 0)
+    gF = gFp[:, P:-P, P:-P]
     ref = O.filter_views(case1.scan, case1.sino[a - 1:b + 2], case1.ftab)[1:-1]
     rel = np.linalg.norm(gF - ref) / np.linalg.norm(ref)
     mx = np.abs(gF - ref).max() / np.abs(ref).max()
@@ -91,7 +95,9 @@ def test_backprojection_stage_parity(case1, plan1):
     a, b = plan1.info["first_view"], plan1.info["last_view"]
     gF64 = O.filter_views(case1.scan, case1.sino[a - 1:b + 2], case1.ftab)[1:-1]
     gF32 = gF64.astype(np.float32)
-    vol = K.backproject(plan1, torch.from_numpy(gF32).to(dev)).cpu().numpy()
+    P = K.katsevich.PAD
+    gF32p = np.pad(gF32, ((0, 0), (P, P), (P, P)))
+    vol = K.backproject(plan1, torch.from_numpy(gF32p).to(dev)).cpu().numpy()
     full = np.zeros((case1.scan.N, case1.scan.rows, case1.scan.cols), np.float32)
     full[a:b + 1] = gF32
     ref = np.zeros_like(vol, dtype=np.float64)
