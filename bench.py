@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bp-slices", type=int, default=0,
+                    help="slices per backprojection register run (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
@@ -105,7 +107,7 @@ def main():
     wl = configs.config2()
     geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
     t0 = time.perf_counter()
-    plan = K.Plan(geom, gr, device=0)
+    plan = K.Plan(geom, gr, device=0, bp_slices=args.bp_slices)
     t_plan = time.perf_counter() - t0
     info = plan.info
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
@@ -182,7 +184,8 @@ def main():
                    "views": geom["n_views"], "views_per_turn": geom["views_per_turn"],
                    "feed_mm_per_turn": geom["feed_per_turn"], "n_psi": info["n_psi"],
                    "pitches": info["n_pitches"], "slices_per_pitch": info["slices_per_pitch"],
-                   "n_vv": n_vv, "filtered_views": n_filt},
+                   "n_vv": n_vv, "filtered_views": n_filt,
+                   "bp_slices": args.bp_slices or 16},
         "volumes_per_s": round(1e3 / ms_step, 3),
         "stage_ms": {"filter": round(float(np.mean(filt_ms)), 4), "backproject": round(bp_avg, 4)},
         "recon_call_ms": round(recon_ms, 4),

@@ -80,9 +80,11 @@ typedef struct katsevich_grid {
 
 /* Plan options.  n_psi: number of kappa-lines sampled uniformly on
  * [-pi/2-alpha_m, pi/2+alpha_m] (eq. FR range; 0 -> 2*det_rows+1; must be >= 3);
- * n_threads: host threads used to build the plan (0 -> all hardware threads). */
+ * n_threads: host threads used to build the plan (0 -> all hardware threads);
+ * flags: reserved, 0; bp_slices: slices per backprojection register run (0 -> 16, else 8,
+ * 16 or 32; a performance knob, results agree to rounding). */
 typedef struct katsevich_options {
-    int32_t n_psi, n_threads, flags, reserved;
+    int32_t n_psi, n_threads, flags, bp_slices;
 } katsevich_options;
 
 typedef struct katsevich_plan_s *katsevich_plan_t;
@@ -100,6 +102,10 @@ typedef struct katsevich_plan_info {
     int32_t window_views;              /* views of one pitch's lambda window W */
     int32_t window_lo;                 /* first window view of pitch 0 (may be < 0) */
     int32_t fft_len, commensurate;     /* Hilbert FFT length; 1 if dz divides P */
+    int32_t gf_rows, gf_cols;          /* padded g^F view of katsevich_filter (see below) */
+    int32_t atan_degree;               /* degree in t^2 of the backprojector's atan polynomial
+                                          (-1: library atan2f) */
+    int32_t reserved;
 } katsevich_plan_info;
 
 /* Table ids for katsevich_plan_export (host copies, for tests). */
@@ -148,9 +154,10 @@ int katsevich_recon(katsevich_plan_t plan, const float *d_sino, float *d_vol,
                     void *d_ws, uint64_t ws_bytes, void *stream);
 
 /* Filtering stage alone (eqs. Deriv, LW, FR, HF, BR, PW): d_sino -> d_gF float32
- * [last_view-first_view+1][rows+2*KATS_GF_PAD][cols+2*KATS_GF_PAD] (filtered_bytes)
- * holding g^F of views first_view..last_view with a zero border of KATS_GF_PAD cells
- * (element [v][r+KATS_GF_PAD][c+KATS_GF_PAD] is detector cell (r, c)).
+ * [last_view-first_view+1][gf_rows][gf_cols] (filtered_bytes) holding g^F of views
+ * first_view..last_view with a zero border: gf_rows = rows + 2*KATS_GF_PAD, gf_cols =
+ * cols + 2*KATS_GF_PAD rounded up to a multiple of 4, element [v][r+KATS_GF_PAD][c+KATS_GF_PAD]
+ * is detector cell (r, c) and every other element is 0.
  * d_ws: at least workspace_bytes_filter.  Asynchronous on stream. */
 #define KATS_GF_PAD 2
 int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF,

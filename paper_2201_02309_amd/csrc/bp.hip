@@ -53,7 +53,6 @@ constexpr int kNT = kT * kT;      // 256 lanes
 constexpr int kLP = 64;           // LDS tile row pitch (floats) = max box columns
 constexpr int kLR = 32;           // max box rows
 constexpr int kLMax = kLP * kLR;  // 2048 floats per buffer
-constexpr int kPF = (kLMax + kNT - 1) / kNT;
 constexpr int kHull = 2048;       // max views of a workgroup hull with per-view group words
 constexpr int kKG = 4;            // slices per branch group
 
@@ -64,7 +63,9 @@ struct BpArgs {
     const BpBox *boxes;
     long long n_views, first_view;
     float R, inv_dalpha, col_c, q_scale, row_c, dz, x_first, y_first, dx, dy, scale;
-    int nx, ny, nz, ns, Nv, n_lo, W, runs, tiles_x, tiles_y, rows, cols;
+    int nx, ny, nz, ns, Nv, n_lo, W, runs, tiles_x, tiles_y, gf_rows, gf_cols;
+    int atan_deg;
+    float atan_coef[9];
 };
 
 __device__ inline float lerp_bilinear(const float *t, int pitch_f, float tc, float tr) {
@@ -76,11 +77,14 @@ __device__ inline float lerp_bilinear(const float *t, int pitch_f, float tc, flo
 
 template <int KZ>
 __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restrict__ gF,
-                                                float *__restrict__ vol) {
-    static_assert(KZ % kKG == 0 && KZ / kKG <= 4, "groups use 4-bit masks");
+                                                float *__restrict__ vol,
+                                                const float4 *__restrict__ view_tab,
+                                                const uint2 *__restrict__ box_tab) {
+    static_assert(KZ % kKG == 0 && KZ / kKG <= 8, "groups use 8-bit masks");
+    static_assert(kLR == 32, "box staging covers 32 rows with two 16-row passes");
     constexpr int NG = KZ / kKG;
-    __shared__ float lds[2][kLMax];
-    __shared__ unsigned char words[4][kHull];   // per wave and view: active groups | full groups << 4
+    __shared__ __attribute__((aligned(16))) float lds[2][kLMax];
+    __shared__ unsigned short words[4][kHull];  // per wave and view: active groups | full groups << 8
     __shared__ int red[8];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -138,8 +142,9 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
         red[4 + wave] = whi;
     }
     __syncthreads();
-    const int mlo = min(min(red[0], red[1]), min(red[2], red[3]));
-    const int mhi = max(max(red[4], red[5]), max(red[6], red[7]));
+    // wave-uniform (scalar) so that the per-view box and view-table reads are scalar loads
+    const int mlo = __builtin_amdgcn_readfirstlane(min(min(red[0], red[1]), min(red[2], red[3])));
+    const int mhi = __builtin_amdgcn_readfirstlane(max(max(red[4], red[5]), max(red[6], red[7])));
     // Per-view group classification of this wave.  A hull longer than kHull views
     // takes the coverage path for every group at every view, which is exact.
     const bool use_words = mhi - mlo + 1 <= kHull;
@@ -150,73 +155,89 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 if (m >= g_alo[g] && m <= g_ahi[g]) word |= 1u << g;
-                if (m >= g_flo[g] && m <= g_fhi[g]) word |= 1u << (4 + g);
+                if (m >= g_flo[g] && m <= g_fhi[g]) word |= 1u << (8 + g);
             }
-            words[wave][w] = (unsigned char)word;
+            words[wave][w] = (unsigned short)word;
         }
     }
 
     const float x = fmaf((float)ix, p.dx, p.x_first);
     const float y = fmaf((float)iy, p.dy, p.y_first);
     const float zoff = (float)j0 * p.dz;
-    const int cpitch = p.cols + 2 * kPad;
-    const size_t vstride = (size_t)(p.rows + 2 * kPad) * cpitch;
-    const BpBox *boxes = p.boxes + ((size_t)(run * p.tiles_y + blockIdx.y) * p.tiles_x +
-                                    blockIdx.x) * p.W;
+    const int cpitch = p.gf_cols;
+    const size_t vstride = (size_t)p.gf_rows * cpitch;
+    // boxes read as two dwords (scalar loads) and unpacked: {r0 | nr << 16, c0 | nc << 16}
+    const uint2 *__restrict__ boxes =
+        box_tab + ((size_t)(run * p.tiles_y + blockIdx.y) * p.tiles_x + blockIdx.x) * p.W;
+    auto unpack = [](uint2 w) {
+        BpBox b;
+        b.r0 = (int16_t)(w.x & 0xffffu);
+        b.nr = (int16_t)(w.x >> 16);
+        b.c0 = (int16_t)(w.y & 0xffffu);
+        b.nc = (int16_t)(w.y >> 16);
+        return b;
+    };
     // g^F of pitch-relative view 0; element (0, 0) of a view is detector cell (-kPad, -kPad)
     const float *gF0 = gF + (size_t)(base - p.first_view) * vstride;
     auto fits = [](const BpBox &b) { return b.nr <= kLR && b.nc <= kLP; };
 
+    // Box staging: 16 lanes per LDS row, one aligned float4 each (the plan starts every box
+    // on a 16-byte boundary of the padded row; columns past the box land in unused LDS).
+    const int srow = tid >> 4, scol = (tid & 15) * 4;
+    uint2 bw_next = make_uint2(0u, 0u);   // box of the view after the current one
     if (mlo <= mhi) {
-        const BpBox b = boxes[mlo];
+        const BpBox b = unpack(boxes[mlo]);
+        if (mlo < mhi) bw_next = boxes[mlo + 1];
         if (fits(b)) {
             const float *src = gF0 + (size_t)mlo * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad);
-            const int n_el = b.nr * b.nc;
-            const float inv_nc = 1.0f / (float)b.nc;
-            for (int e = tid; e < n_el; e += kNT) {
-                const int r = (int)(((float)e + 0.5f) * inv_nc);
-                const int c = e - r * b.nc;
-                lds[0][r * kLP + c] = src[r * cpitch + c];
-            }
+            if (srow < b.nr && scol < b.nc)
+                *reinterpret_cast<float4 *>(&lds[0][srow * kLP + scol]) =
+                    *reinterpret_cast<const float4 *>(src + srow * cpitch + scol);
+            if (srow + 16 < b.nr && scol < b.nc)
+                *reinterpret_cast<float4 *>(&lds[0][(srow + 16) * kLP + scol]) =
+                    *reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol);
         }
     }
     __syncthreads();
+    BpBox b = unpack(boxes[mlo <= mhi ? mlo : 0]);
     for (int m = mlo; m <= mhi; ++m) {
         const int buf = (m - mlo) & 1;
-        const BpBox b = boxes[m];
-        // prefetch the next view's box into registers
-        float pf[kPF];
+        // box of view m+2, loaded one iteration ahead of its use
+        const uint2 bw_after = (m + 2 <= mhi) ? boxes[m + 2] : make_uint2(0u, 0u);
+        // prefetch the next view's box into registers (two rows of 16 float4 lanes)
+        float4 pf0, pf1;
         BpBox bn = b;
-        bool next_fits = false;
-        int n_next = 0;
-        float inv_nc_next = 1.0f;
+        bool next_fits = false, st0 = false, st1 = false;
         if (m < mhi) {
-            bn = boxes[m + 1];
+            bn = unpack(bw_next);
             next_fits = fits(bn);
             if (next_fits) {
-                n_next = bn.nr * bn.nc;
-                inv_nc_next = 1.0f / (float)bn.nc;
                 const float *src = gF0 + (size_t)(m + 1) * vstride + (bn.r0 + kPad) * cpitch + (bn.c0 + kPad);
-#pragma unroll
-                for (int k = 0; k < kPF; ++k) {
-                    const int e = tid + k * kNT;
-                    if (e < n_next) {
-                        const int r = (int)(((float)e + 0.5f) * inv_nc_next);
-                        const int c = e - r * bn.nc;
-                        pf[k] = src[r * cpitch + c];
-                    }
-                }
+                st0 = srow < bn.nr && scol < bn.nc;
+                st1 = srow + 16 < bn.nr && scol < bn.nc;
+                if (st0) pf0 = *reinterpret_cast<const float4 *>(src + srow * cpitch + scol);
+                if (st1) pf1 = *reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol);
             }
         }
         // per (lane, view) geometry; coordinates relative to the box origin, clamped into
         // the box (only voxels projecting outside the zero-padded detector are clamped)
-        const float4 vt = p.view[m];
+        const float4 vt = view_tab[m];
         const float u = fmaf(-x, vt.y, y * vt.x);
         const float v = p.R - fmaf(x, vt.x, y * vt.y);
         const float vinv = __builtin_amdgcn_rcpf(v);
         const float rinv = __builtin_amdgcn_rsqf(fmaf(u, u, v * v));
-        const float cc = med3(fmaf(atan2f(u, v), p.inv_dalpha, p.col_c - (float)b.c0), 0.0f,
-                              (float)(b.nc - 2));
+        float acol;                                          // alpha* / dalpha
+        if (p.atan_deg >= 0) {
+            const float t = u * vinv;                        // tan(alpha*)
+            const float s2 = t * t;
+            float qa = p.atan_coef[8];
+#pragma unroll
+            for (int k = 7; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
+            acol = t * qa;
+        } else {
+            acol = atan2f(u, v) * p.inv_dalpha;
+        }
+        const float cc = med3(acol + (p.col_c - (float)b.c0), 0.0f, (float)(b.nc - 2));
         const int c0 = (int)cc;
         const float tc = cc - (float)c0;
         const float q = p.q_scale * rinv;                   // detector rows per mm of z
@@ -236,7 +257,7 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
                 const int r0 = (int)rr;               // rr >= 0: truncation = floor
                 val[s] = lerp_bilinear(T + r0 * tp, tp, tc, __builtin_amdgcn_fractf(rr));
             }
-            if (word & (1u << (4 + g))) {
+            if (word & (1u << (8 + g))) {
 #pragma unroll
                 for (int s = 0; s < kKG; ++s) acc[g * kKG + s] = fmaf(vinv, val[s], acc[g * kKG + s]);
             } else {
@@ -259,18 +280,13 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
             for (int g = 0; g < NG; ++g)
                 if (word & (1u << g)) group(T, cpitch, g);
         }
-        if (next_fits) {
+        {
             float *Dst = lds[buf ^ 1];
-#pragma unroll
-            for (int k = 0; k < kPF; ++k) {
-                const int e = tid + k * kNT;
-                if (e < n_next) {
-                    const int r = (int)(((float)e + 0.5f) * inv_nc_next);
-                    const int c = e - r * bn.nc;
-                    Dst[r * kLP + c] = pf[k];
-                }
-            }
+            if (st0) *reinterpret_cast<float4 *>(&Dst[srow * kLP + scol]) = pf0;
+            if (st1) *reinterpret_cast<float4 *>(&Dst[(srow + 16) * kLP + scol]) = pf1;
         }
+        b = bn;
+        bw_next = bw_after;
         __syncthreads();
     }
     if (!inxy) return;
@@ -402,9 +418,18 @@ hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hip
     a.runs = k.bp_runs;
     a.tiles_x = k.bp_tiles_x;
     a.tiles_y = k.bp_tiles_y;
-    a.rows = k.rows;
-    a.cols = k.cols;
-    hipLaunchKernelGGL(k_bp_lds<kBpKZ>, grid, dim3(kNT), 0, s, a, gF, vol);
+    a.gf_rows = k.gf_rows;
+    a.gf_cols = k.gf_cols;
+    a.atan_deg = k.atan_deg;
+    for (int i = 0; i < 9; ++i) a.atan_coef[i] = k.atan_coef[i];
+    switch (k.bp_kz) {
+        case 8: hipLaunchKernelGGL(k_bp_lds<8>, grid, dim3(kNT), 0, s, a, gF, vol, k.view,
+                                        reinterpret_cast<const uint2 *>(k.boxes)); break;
+        case 32: hipLaunchKernelGGL(k_bp_lds<32>, grid, dim3(kNT), 0, s, a, gF, vol, k.view,
+                                        reinterpret_cast<const uint2 *>(k.boxes)); break;
+        default: hipLaunchKernelGGL(k_bp_lds<16>, grid, dim3(kNT), 0, s, a, gF, vol, k.view,
+                                        reinterpret_cast<const uint2 *>(k.boxes)); break;
+    }
     return hipGetLastError();
 }
 

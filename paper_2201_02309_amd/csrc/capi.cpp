@@ -89,6 +89,11 @@ KParams make_params(const PlanHost &P) {
     k.bp_tiles_x = P.bp_tiles_x;
     k.bp_tiles_y = P.bp_tiles_y;
     k.bp_runs = P.bp_runs;
+    k.bp_kz = P.bp_kz;
+    k.gf_rows = P.gf_rows;
+    k.gf_cols = P.gf_cols;
+    k.atan_deg = P.atan_deg;
+    for (int i = 0; i < 9; ++i) k.atan_coef[i] = P.atan_coef[i];
     return k;
 }
 
@@ -163,6 +168,9 @@ int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
     i.window_lo = P.n_lo;
     i.fft_len = P.fft_len;
     i.commensurate = P.commensurate ? 1 : 0;
+    i.gf_rows = P.gf_rows;
+    i.gf_cols = P.gf_cols;
+    i.atan_degree = P.atan_deg;
     *out = i;
     return KATS_OK;
 }

@@ -147,13 +147,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fr_hilbert(KParams p, const flo
     }
 }
 
-// Writes the zero-padded view [rows + 2 kPad][cols + 2 kPad] (border = 0).
+// Writes the zero-padded view [gf_rows][gf_cols] (border = 0).
 __global__ __launch_bounds__(kElemThreads) void k_br_cos(KParams p, const float *__restrict__ g4,
                                                          float *__restrict__ gF) {
     const long long i = blockIdx.x;
     const int rp = blockIdx.y;
     const int cp = blockIdx.z * kElemThreads + threadIdx.x;
-    const int pitch = p.cols + 2 * kPad;
+    const int pitch = p.gf_cols;
     if (cp >= pitch) return;
     const int r = rp - kPad, c = cp - kPad;
     float out = 0.0f;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kElemThreads) void k_br_cos(KParams p, const float 
         const float b = v4[(k0 + 1) * p.cols + c];
         out = p.cos_alpha[c] * ((1.0f - t) * a + t * b);
     }
-    gF[((size_t)i * (p.rows + 2 * kPad) + rp) * pitch + cp] = out;
+    gF[((size_t)i * p.gf_rows + rp) * pitch + cp] = out;
 }
 
 // ----------------------------------------------------------------------------- adjoint
@@ -287,8 +287,8 @@ hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *
     const size_t lds = (size_t)3 * k.fft_len * sizeof(float2);
     hipLaunchKernelGGL(k_fr_hilbert, dim3((unsigned)(k.n_filt * n_pairs)), dim3(kFftThreads), lds, s,
                        k, g2, g4);
-    const int cbp = (k.cols + 2 * kPad + kElemThreads - 1) / kElemThreads;
-    hipLaunchKernelGGL(k_br_cos, dim3((unsigned)k.n_filt, k.rows + 2 * kPad, cbp), dim3(kElemThreads),
+    const int cbp = (k.gf_cols + kElemThreads - 1) / kElemThreads;
+    hipLaunchKernelGGL(k_br_cos, dim3((unsigned)k.n_filt, k.gf_rows, cbp), dim3(kElemThreads),
                        0, s, k, g4, gF);
     return hipGetLastError();
 }

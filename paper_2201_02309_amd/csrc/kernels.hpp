@@ -35,7 +35,10 @@ struct KParams {
     const float *hil_im;
     const PiEntry *pi;
     const BpBox *boxes;
-    int bp_tiles_x, bp_tiles_y, bp_runs;
+    int bp_tiles_x, bp_tiles_y, bp_runs, bp_kz;
+    int gf_rows, gf_cols;              // padded g^F view (zero border kPad)
+    int atan_deg;                      // < 0: atan2f
+    float atan_coef[9];                // alpha/dalpha = t * sum_k atan_coef[k] t^(2k)
 };
 
 KParams make_params(const PlanHost &P);

@@ -132,6 +132,62 @@ void parallel_for(int n, int threads, Fn fn) {
     for (auto &th : pool) th.join();
 }
 
+// Odd polynomial for alpha / dalpha = atan(t) / dalpha on |t| <= T: interpolate
+// f(sigma) = atan(t)/t, s = t^2 = sigma T^2, at the d+1 Chebyshev points of sigma in [0, 1]
+// (Vandermonde solve in long double), scale by 1/dalpha, round to float32, and accept the
+// lowest degree whose float32 Horner evaluation t * (c0 + s (c1 + ...)) stays within 4 ulp
+// of the largest column coordinate over a dense grid of t.
+bool fit_atan_columns(double T, double inv_dalpha, float coef[9], int &deg) {
+    const double S = T * T;
+    const double ymax = std::atan(T) * inv_dalpha;
+    const double tol = 4.0 * std::ldexp(1.0, std::ilogb(ymax) - 23);
+    for (int d = 2; d <= 8; ++d) {
+        const int n = d + 1;
+        long double M[9][10];
+        for (int i = 0; i < n; ++i) {
+            const long double sig = 0.5L + 0.5L * std::cos((2.0L * i + 1.0L) * (long double)kPi / (2.0L * n));
+            const long double t = std::sqrt(sig * (long double)S);
+            const long double f = (t == 0.0L) ? 1.0L : std::atan(t) / t;
+            long double pw = 1.0L;
+            for (int k = 0; k < n; ++k) { M[i][k] = pw; pw *= sig; }
+            M[i][n] = f;
+        }
+        for (int c = 0; c < n; ++c) {                 // Gaussian elimination, partial pivoting
+            int piv = c;
+            for (int r = c + 1; r < n; ++r)
+                if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+            for (int k = 0; k <= n; ++k) std::swap(M[c][k], M[piv][k]);
+            for (int r = 0; r < n; ++r) {
+                if (r == c) continue;
+                const long double fct = M[r][c] / M[c][c];
+                for (int k = c; k <= n; ++k) M[r][k] -= fct * M[c][k];
+            }
+        }
+        float cf[9] = {0};
+        long double sk = 1.0L;
+        for (int k = 0; k < n; ++k) {                 // sigma^k = s^k / S^k
+            cf[k] = (float)((M[k][n] / M[k][k]) / sk * (long double)inv_dalpha);
+            sk *= (long double)S;
+        }
+        double err = 0.0;
+        for (int i = 0; i <= 20000; ++i) {
+            const float t = (float)(-T + 2.0 * T * i / 20000.0);
+            const float ss = t * t;
+            float q = cf[d];
+            for (int k = d - 1; k >= 0; --k) q = std::fmaf(q, ss, cf[k]);
+            const float y = t * q;
+            err = std::max(err, std::fabs((double)y - std::atan((double)t) * inv_dalpha));
+        }
+        if (err <= tol) {
+            for (int k = 0; k < 9; ++k) coef[k] = cf[k];
+            deg = d;
+            return true;
+        }
+    }
+    deg = -1;
+    return false;
+}
+
 }  // namespace
 
 bool voxel_valid(const PlanHost &P, int iz, int iy, int ix) {
@@ -158,6 +214,9 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     if (gr.nx < 1 || gr.ny < 1 || gr.nz < 1) return bad("grid sizes must be >= 1");
     if (!(gr.dx > 0) || !(gr.dy > 0) || !(gr.dz > 0)) return bad("grid spacings must be > 0");
     if (opts.n_psi != 0 && opts.n_psi < 3) return bad("n_psi must be 0 or >= 3");
+    if (opts.bp_slices != 0 && opts.bp_slices != 8 && opts.bp_slices != 16 && opts.bp_slices != 32)
+        return bad("bp_slices must be 0, 8, 16 or 32");
+    P.bp_kz = opts.bp_slices ? opts.bp_slices : kBpKZ;
 
     const int cols = g.det_cols, rows = g.det_rows;
     P.h = g.feed_per_turn / kTwoPi;
@@ -362,7 +421,7 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     L.pi = take((uint64_t)nvox * sizeof(PiEntry));
     P.bp_tiles_x = (gr.nx + kBpTile - 1) / kBpTile;
     P.bp_tiles_y = (gr.ny + kBpTile - 1) / kBpTile;
-    P.bp_runs = (P.n_tab + kBpKZ - 1) / kBpKZ;
+    P.bp_runs = (P.n_tab + P.bp_kz - 1) / P.bp_kz;
     const uint64_t n_boxes = (uint64_t)P.bp_runs * P.bp_tiles_y * P.bp_tiles_x * P.W;
     L.boxes = take(n_boxes * sizeof(BpBox));
     L.total = off;
@@ -442,8 +501,8 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
             const double x1 = gr.x_first + (double)(tx * kBpTile + kBpTile - 1) * gr.dx;
             const double y0 = gr.y_first + (double)ty * kBpTile * gr.dy;
             const double y1 = gr.y_first + (double)(ty * kBpTile + kBpTile - 1) * gr.dy;
-            const double zs0 = (double)(run * kBpKZ) * gr.dz;
-            const double zs1 = (double)(run * kBpKZ + kBpKZ - 1) * gr.dz;
+            const double zs0 = (double)(run * P.bp_kz) * gr.dz;
+            const double zs1 = (double)(run * P.bp_kz + P.bp_kz - 1) * gr.dz;
             const double cx[4] = {x0, x1, x0, x1}, cy[4] = {y0, y0, y1, y1};
             BpBox *out = bx + (size_t)t * P.W;
             for (int m = 0; m < P.W; ++m) {
@@ -480,7 +539,11 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
                     return std::make_pair(ia, ic - ia + 1);
                 };
                 const auto rr = clip(wlo / g.dw + row_c, whi / g.dw + row_c, rows);
-                const auto cc = clip(amin / g.dalpha + col_c, amax / g.dalpha + col_c, cols);
+                auto cc = clip(amin / g.dalpha + col_c, amax / g.dalpha + col_c, cols);
+                // start the columns on a 16-byte boundary of the padded view row
+                const int shift = (cc.first + kPad) & 3;
+                cc.first -= shift;
+                cc.second += shift;
                 out[m].r0 = (int16_t)rr.first;
                 out[m].nr = (int16_t)rr.second;
                 out[m].c0 = (int16_t)cc.first;
@@ -493,7 +556,14 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     const int64_t nfilt = std::max<int64_t>(0, P.last_view - P.first_view + 1);
     P.g4_bytes = align256((uint64_t)nfilt * P.n_psi * cols * 4);
     P.g2_bytes = align256((uint64_t)nfilt * rows * cols * 4);
-    P.gF_bytes = align256((uint64_t)nfilt * (rows + 2 * kPad) * (cols + 2 * kPad) * 4);
+    P.gf_rows = rows + 2 * kPad;
+    P.gf_cols = (cols + 2 * kPad + 3) & ~3;
+    P.gF_bytes = align256((uint64_t)nfilt * P.gf_rows * P.gf_cols * 4);
+
+    // ------------------------------------------------------------------ atan polynomial
+    // |tan(alpha*)| <= tan(alpha_m) for every voxel inside the field of view; other lanes
+    // are discarded (and clamped into their box), so a fit on that range is exact enough
+    fit_atan_columns(std::tan(P.alpha_m) * (1.0 + 1e-4), 1.0 / g.dalpha, P.atan_coef, P.atan_deg);
     return KATS_OK;
 }
 

@@ -27,7 +27,7 @@ struct PiEntry {
 static_assert(sizeof(PiEntry) == 16, "PiEntry must be 16 bytes");
 
 // Backprojection tiling: a workgroup owns a kBpTile x kBpTile (x, y) tile and a run of
-// kBpKZ consecutive slices of one pitch.
+// bp_kz consecutive slices of one pitch (8, 16 or 32; kBpKZ by default).
 constexpr int kBpTile = 16;
 constexpr int kBpKZ = 16;
 // Rows / columns of zero padding around every filtered view g^F (so that clamped
@@ -83,7 +83,7 @@ struct PlanHost {
     std::vector<int32_t> pi_nf, pi_nl;     // global view indices, pitch 0
     std::vector<uint8_t> fov;
     int32_t n_lo = 0, n_hi = 0, W = 0;
-    int bp_tiles_x = 0, bp_tiles_y = 0, bp_runs = 0;
+    int bp_tiles_x = 0, bp_tiles_y = 0, bp_runs = 0, bp_kz = kBpKZ;
     int64_t first_view = 0, last_view = -1, n_vv = 0, n_valid = 0;
 
     // Hilbert
@@ -94,6 +94,14 @@ struct PlanHost {
     TableLayout layout;
     std::vector<unsigned char> image;      // table_bytes, copied by katsevich_plan_bind
     void *d_tables = nullptr;              // caller memory after bind
+
+    // padded g^F view: [gf_rows][gf_cols], gf_cols a multiple of 4 (16-byte rows)
+    int gf_rows = 0, gf_cols = 0;
+
+    // column coordinate alpha*/dalpha as an odd polynomial t * P(t^2) of t = tan(alpha*)
+    // (fitted on the detector's fan range); atan_deg < 0: use the library atan2f
+    float atan_coef[9] = {0};
+    int atan_deg = -1;
 
     // workspace layout (bytes)
     uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0;   // gF: padded [n][rows+2kPad][cols+2kPad]

@@ -39,7 +39,7 @@ class _Grid(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("n_psi", c_int32), ("n_threads", c_int32), ("flags", c_int32),
-                ("reserved", c_int32)]
+                ("bp_slices", c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -49,7 +49,8 @@ class _Info(ctypes.Structure):
                 ("n_valid_voxels", c_int64), ("n_pitches", c_int32),
                 ("slices_per_pitch", c_int32), ("n_table_slices", c_int32), ("n_psi", c_int32),
                 ("window_views", c_int32), ("window_lo", c_int32), ("fft_len", c_int32),
-                ("commensurate", c_int32)]
+                ("commensurate", c_int32), ("gf_rows", c_int32), ("gf_cols", c_int32),
+                ("atan_degree", c_int32), ("reserved", c_int32)]
 
 
 # table id -> (C enum, numpy dtype, shape key)
@@ -134,12 +135,13 @@ class Plan:
     geom / grid: dicts with the fields of katsevich_geometry / katsevich_grid."""
 
     def __init__(self, geom: dict, grid: dict, n_psi: int = 0, n_threads: int = 0,
-                 bind: bool = True, device=None):
+                 bind: bool = True, device=None, bp_slices: int = 0):
         self._lib = load_library()
         self.geom = dict(geom)
         self.grid = dict(grid)
         self._h = c_void_p()
-        opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads), flags=0, reserved=0)
+        opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads), flags=0,
+                        bp_slices=int(bp_slices))
         g, gr = _geom_struct(geom), _grid_struct(grid)
         _check(self._lib, self._lib.katsevich_plan(byref(g), byref(gr), byref(opts),
                                                    byref(self._h)))
@@ -248,9 +250,9 @@ PAD = 2   # zero border (cells) around every filtered view, see include/katsevic
 
 
 def filtered_shape(plan: Plan):
-    """Shape of the g^F buffer: [n_filtered, rows + 2 PAD, cols + 2 PAD]."""
-    return (plan.n_filtered, int(plan.geom["det_rows"]) + 2 * PAD,
-            int(plan.geom["det_cols"]) + 2 * PAD)
+    """Shape of the g^F buffer: [n_filtered, gf_rows, gf_cols] (zero border of PAD cells;
+    gf_cols is cols + 2 PAD rounded up to a multiple of 4)."""
+    return (plan.n_filtered, int(plan.info["gf_rows"]), int(plan.info["gf_cols"]))
 
 
 def filter_views(plan: Plan, sino, out=None, ws=None):

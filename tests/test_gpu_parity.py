@@ -133,6 +133,18 @@ def test_recon_parity_config1(case1, plan1):
     assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * case1.peak
 
 
+@pytest.mark.parametrize("bp_slices", [8, 32])
+def test_recon_parity_slice_run_variants(case1, bp_slices):
+    """The 8- and 32-slice backprojection kernels meet the same bar as the default."""
+    dev = _dev()
+    plan = K.Plan(case1.geom, case1.grid, device=0, bp_slices=bp_slices)
+    vol = K.recon(plan, torch.from_numpy(case1.sino).to(dev)).cpu().numpy()
+    ref, valid = case1.ref
+    rel, mx = _report(f"recon config1 bp_slices={bp_slices}", vol, ref, valid, case1.peak)
+    assert np.all(vol[~valid] == 0)
+    assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * case1.peak
+
+
 @pytest.mark.parametrize("shape", [(13, 11, 29), (9, 17, 5), (1, 1, 3)])
 def test_recon_ragged_grids(shape):
     """Grids that are not multiples of the 8 x 8 tile or of the slice run, spanning pitch
