@@ -81,6 +81,23 @@ def cpu_baseline(wl, budget_views=None):
             "finite": bool(np.isfinite(f).all())}
 
 
+def _measured_traffic():
+    """HBM bytes per backprojection launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (scaled by a plain-copy calibration), or None when the kernel or
+    plan sources changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "bp_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    h = hashlib.sha256()
+    for src in tr.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return tr.get("bytes_per_launch") if h.hexdigest() == tr.get("source_sha256") else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,13 +175,7 @@ def main():
 
     bp_avg = float(np.mean(bp_ms))
     achieved = n_vv * BP_FLOP_PER_UPDATE / (bp_avg * 1e-3) / 1e12
-    traffic = None
-    tr_path = os.path.join(ROOT, "profiles", "bp_traffic.json")
-    if os.path.exists(tr_path):
-        with open(tr_path) as f:
-            tr = json.load(f)
-        if tr.get("kernel_hash") == "current":
-            traffic = tr.get("bytes_per_launch")
+    traffic = _measured_traffic()
     out = {
         "metric": "Gvoxel-view/s (512^2x128 clinical high-pitch Katsevich recon)",
         "value": round(value, 3),
