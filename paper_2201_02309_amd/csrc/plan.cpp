@@ -47,48 +47,74 @@ double bisect_increasing(F f, double lo, double hi) {
 }
 
 // ---------------------------------------------------------------------------------
-// PI lines.  For source angle b1 = s + lambda0 the in-plane chord through X = (x, y)
-// ends at b1 + 2 theta with tan(theta) = (R - rho cos(phi - b1)) / (rho sin(phi - b1))
-// (the chord's distance to the axis is R cos(theta) and its normal points at
-// b1 + theta); X sits at fraction t = (X - S1).(S2 - S1) / |S2 - S1|^2 along it.
-// lambda_i = s solves z0 + h (s + t * 2 theta) = z.
+// PI lines.  For source angle b1 = s + lambda0 and X = (x, y) = rho (cos phi, sin phi),
+// d = phi - b1, the in-plane chord from the source through X ends at b1 + 2 theta with
+// theta = atan2(A, B), A = R - rho cos d, B = rho sin d (the chord lies at distance
+// R cos(theta) from the axis, normal direction b1 + theta).  Along the chord direction
+// e(b1 + theta + pi/2), X sits at fraction t = 1/2 + rho (B cos d ... ) / (2 R sin theta),
+// i.e. t = 1/2 + rho (sin d * B - cos d * A) / (2 R A).  lambda_i = s solves
+// z0 + h (s + 2 theta t) = z.
 // ---------------------------------------------------------------------------------
 struct PiSolver {
     double R, h, lambda0, z0;
 
-    void chord(double s, double x, double y, double &span, double &t) const {
-        const double b1 = s + lambda0;
-        const double rho = std::hypot(x, y);
-        const double phi = std::atan2(y, x);
-        const double d = phi - b1;
-        const double th = std::atan2(R - rho * std::cos(d), rho * std::sin(d));   // (0, pi)
-        span = 2.0 * th;
-        const double c1 = std::cos(b1), s1 = std::sin(b1);
-        const double c2 = std::cos(b1 + span), s2 = std::sin(b1 + span);
-        const double ex = R * (c2 - c1), ey = R * (s2 - s1);
-        t = ((x - R * c1) * ex + (y - R * s1) * ey) / (ex * ex + ey * ey);
-    }
-
-    double height_gap(double s, double x, double y, double z) const {
-        double span, t;
-        chord(s, x, y, span, t);
+    double height_gap(double s, double rho, double phi, double z, double &span) const {
+        const double d = phi - (s + lambda0);
+        const double sd = std::sin(d), cd = std::cos(d);
+        const double A = R - rho * cd, B = rho * sd;
+        span = 2.0 * std::atan2(A, B);                      // (0, 2 pi)
+        const double t = 0.5 + rho * (sd * B - cd * A) / (2.0 * R * A);
         return z0 + h * (s + t * span) - z;
     }
 
-    // Illinois-modified regula falsi on the bracket ((z-z0)/h - 2pi, (z-z0)/h).
-    void solve(double x, double y, double z, double &li, double &lo) const {
+    // height gap and its derivative in s (dd/ds = -1):
+    // dA/ds = -rho sin d, dB/ds = -rho cos d, dtheta/ds = rho (A cos d - B sin d)/(A^2+B^2),
+    // N = sin d B - cos d A, dN/ds = -(cos d B + sin d A), t = 1/2 + rho N / (2 R A).
+    double height_gap_d(double s, double rho, double phi, double z, double &span,
+                        double &deriv) const {
+        const double d = phi - (s + lambda0);
+        const double sd = std::sin(d), cd = std::cos(d);
+        const double A = R - rho * cd, B = rho * sd;
+        const double th = std::atan2(A, B);
+        span = 2.0 * th;
+        const double N = sd * B - cd * A;
+        const double t = 0.5 + rho * N / (2.0 * R * A);
+        const double dth = rho * (A * cd - B * sd) / (A * A + B * B);
+        const double dA = -rho * sd;
+        const double dN = -(cd * B + sd * A);
+        const double dt = rho / (2.0 * R) * (dN * A - N * dA) / (A * A);
+        deriv = h * (1.0 + dt * span + t * 2.0 * dth);
+        return z0 + h * (s + t * span) - z;
+    }
+
+    // Newton from a close guess, kept inside the domain; false if it does not settle
+    // within a few steps (the caller then brackets).
+    bool newton(double guess, double rho, double phi, double z, double &root) const {
         const double zr = (z - z0) / h;
-        double a = zr - kTwoPi, b = zr;
-        double fa = height_gap(a, x, y, z), fb = height_gap(b, x, y, z);
-        double s = 0.5 * (a + b);
+        double s = guess, span, der;
+        for (int it = 0; it < 8; ++it) {
+            const double f = height_gap_d(s, rho, phi, z, span, der);
+            if (f == 0.0) { root = s; return true; }
+            if (!(der > 0.0)) return false;
+            const double sn = s - f / der;
+            if (!(sn > zr - kTwoPi && sn < zr)) return false;
+            if (std::fabs(sn - s) <= 2e-16 * std::max(1.0, std::fabs(s))) { root = sn; return true; }
+            s = sn;
+        }
+        return false;
+    }
+
+    // Illinois-modified regula falsi on a bracket [a, b] with F(a) < 0 < F(b).
+    double illinois(double a, double fa, double b, double fb, double rho, double phi,
+                    double z) const {
+        double s = 0.5 * (a + b), span;
         int side = 0;
         for (int it = 0; it < 200; ++it) {
-            if (!(fa < 0 && fb > 0)) break;
             s = b - fb * (b - a) / (fb - fa);
             if (!(s > a && s < b)) s = 0.5 * (a + b);
             if (!(s > a && s < b)) break;                 // bracket at float64 resolution
-            const double fs = height_gap(s, x, y, z);
-            if (fs == 0.0) { a = b = s; break; }
+            const double fs = height_gap(s, rho, phi, z, span);
+            if (fs == 0.0) return s;
             if (fs < 0) {
                 a = s; fa = fs;
                 if (side == -1) fb *= 0.5;
@@ -100,9 +126,47 @@ struct PiSolver {
             }
             if (b - a <= 4e-16 * std::max(1.0, std::fabs(s))) break;
         }
-        s = (a == b) ? a : s;
-        double span, t;
-        chord(s, x, y, span, t);
+        return s;
+    }
+
+    // Root on ((z-z0)/h - 2pi, (z-z0)/h); a previous root s_prev of a lower z (same
+    // x, y) is a lower bound, since lambda_i increases with z.
+    void solve(double x, double y, double z, double &li, double &lo, const double *s_prev,
+               double step, const double *guess = nullptr) const {
+        const double rho = std::hypot(x, y), phi = std::atan2(y, x);
+        const double zr = (z - z0) / h;
+        double span;
+        double root;
+        if (guess && newton(*guess, rho, phi, z, root)) {
+            height_gap(root, rho, phi, z, span);
+            li = root;
+            lo = root + span;
+            return;
+        }
+        double a = zr - kTwoPi, b = zr;
+        double fa, fb;
+        bool have = false;
+        if (s_prev && *s_prev > a && *s_prev < b) {
+            fa = height_gap(*s_prev, rho, phi, z, span);
+            if (fa < 0) {
+                a = *s_prev;
+                for (double w = step; !have; w *= 4.0) {
+                    const double hi = std::min(a + w, zr);
+                    fb = height_gap(hi, rho, phi, z, span);
+                    if (fb > 0) { b = hi; have = true; }
+                    else if (hi >= zr) break;
+                    else { a = hi; fa = fb; }
+                }
+            }
+        }
+        if (!have) {
+            a = zr - kTwoPi;
+            b = zr;
+            fa = height_gap(a, rho, phi, z, span);
+            fb = height_gap(b, rho, phi, z, span);
+        }
+        const double s = (fa < 0 && fb > 0) ? illinois(a, fa, b, fb, rho, phi, z) : 0.5 * (a + b);
+        height_gap(s, rho, phi, z, span);
         li = s;
         lo = s + span;
     }
@@ -331,15 +395,21 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     }
     const PiSolver S{g.R, P.h, g.lambda0, g.z0};
     const double r2 = P.r_fov * P.r_fov;
-    parallel_for(P.n_tab * gr.ny, threads_for(opts), [&](int jy) {
-        const int j = jy / gr.ny, iy = jy % gr.ny;
-        const double z = gr.z_first + j * gr.dz;
+    // per voxel column (x, y), slices in increasing z so each root brackets the next
+    const double step = 2.0 * gr.dz / P.h;
+    parallel_for(gr.ny, threads_for(opts), [&](int iy) {
         const double y = gr.y_first + iy * gr.dy;
         for (int ix = 0; ix < gr.nx; ++ix) {
-            const double x = gr.x_first + ix * gr.dx;
+          const double x = gr.x_first + ix * gr.dx;
+          double prev = 0.0, prev2 = 0.0;
+          for (int j = 0; j < P.n_tab; ++j) {
+            const double z = gr.z_first + j * gr.dz;
             const size_t e = (size_t)j * plane + (size_t)iy * gr.nx + ix;
             double li, lo;
-            S.solve(x, y, z, li, lo);
+            const double guess = 2.0 * prev - prev2;         // linear extrapolation in z
+            S.solve(x, y, z, li, lo, j > 0 ? &prev : nullptr, step, j > 1 ? &guess : nullptr);
+            prev2 = prev;
+            prev = li;
             const double vi = (li - g.lambda_first) / P.dlam;
             const double vo = (lo - g.lambda_first) / P.dlam;
             P.pi_li[e] = vi;
@@ -347,6 +417,7 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
             P.pi_nf[e] = (int32_t)(std::floor(vi - 0.5) + 1.0);
             P.pi_nl[e] = (int32_t)(std::ceil(vo + 0.5) - 1.0);
             P.fov[e] = (x * x + y * y <= r2) ? 1 : 0;
+          }
         }
     });
 
@@ -467,7 +538,10 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     {
         PiEntry *pe = reinterpret_cast<PiEntry *>(img + L.pi);
         constexpr int32_t kEmptyLo = 1 << 29;
-        for (size_t e = 0; e < nvox; ++e) {
+        const int chunks = 64;
+        parallel_for(chunks, threads_for(opts), [&](int ch) {
+        const size_t e0 = nvox * ch / chunks, e1 = nvox * (ch + 1) / chunks;
+        for (size_t e = e0; e < e1; ++e) {
             if (P.fov[e]) {
                 pe[e].li = (float)(P.pi_li[e] - P.n_lo);
                 pe[e].lo = (float)(P.pi_lo[e] - P.n_lo);
@@ -480,6 +554,7 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
                 pe[e].nl = -kEmptyLo;
             }
         }
+        });
     }
 
     // ------------------------------------------------------------------ footprint boxes
@@ -492,19 +567,27 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
         BpBox *bx = reinterpret_cast<BpBox *>(img + L.boxes);
         const double col_c = 0.5 * (cols - 1) - g.col_offset;
         const double row_c = 0.5 * (rows - 1) - g.row_offset;
-        const int tiles = P.bp_runs * P.bp_tiles_y * P.bp_tiles_x;
+        const int tiles = P.bp_tiles_y * P.bp_tiles_x;
         parallel_for(tiles, threads_for(opts), [&](int t) {
             const int tx = t % P.bp_tiles_x;
-            const int ty = (t / P.bp_tiles_x) % P.bp_tiles_y;
-            const int run = t / (P.bp_tiles_x * P.bp_tiles_y);
+            const int ty = t / P.bp_tiles_x;
             const double x0 = gr.x_first + (double)tx * kBpTile * gr.dx;
             const double x1 = gr.x_first + (double)(tx * kBpTile + kBpTile - 1) * gr.dx;
             const double y0 = gr.y_first + (double)ty * kBpTile * gr.dy;
             const double y1 = gr.y_first + (double)(ty * kBpTile + kBpTile - 1) * gr.dy;
-            const double zs0 = (double)(run * P.bp_kz) * gr.dz;
-            const double zs1 = (double)(run * P.bp_kz + P.bp_kz - 1) * gr.dz;
             const double cx[4] = {x0, x1, x0, x1}, cy[4] = {y0, y0, y1, y1};
-            BpBox *out = bx + (size_t)t * P.W;
+            auto clip = [](double lo, double hi, int n) {
+                // cells [lo, hi] clipped to [-kPad, n-1+kPad], at least two cells
+                double a = std::floor(lo) - 1.0, c = std::floor(hi) + 2.0;
+                a = std::max(a, (double)-kPad);
+                c = std::min(c, (double)(n - 1 + kPad));
+                int ia = (int)std::min(a, 1e6), ic = (int)std::max(c, -1e6);
+                if (ic - ia < 1) {
+                    if (ia >= n) { ia = n + kPad - 2; ic = n + kPad - 1; }
+                    else { ia = -kPad; ic = -kPad + 1; }
+                }
+                return std::make_pair(ia, ic - ia + 1);
+            };
             for (int m = 0; m < P.W; ++m) {
                 const double lam = g.lambda_first + (double)(P.n_lo + m) * P.dlam;
                 const double b = lam + g.lambda0;
@@ -522,32 +605,24 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
                 const double ddx = std::max({x0 - Sx, 0.0, Sx - x1});
                 const double ddy = std::max({y0 - Sy, 0.0, Sy - y1});
                 const double rmin = std::max(std::hypot(ddx, ddy), 1e-9);
-                const double e = gr.z_first - g.z0 - P.h * lam;
-                const double dz0 = e + zs0, dz1 = e + zs1;
-                const double wlo = g.D * dz0 / (dz0 >= 0 ? rmax : rmin);
-                const double whi = g.D * dz1 / (dz1 >= 0 ? rmin : rmax);
-                auto clip = [](double lo, double hi, int n) {
-                    // cells [lo, hi] clipped to [-kPad, n-1+kPad], at least two cells
-                    double a = std::floor(lo) - 1.0, c = std::floor(hi) + 2.0;
-                    a = std::max(a, (double)-kPad);
-                    c = std::min(c, (double)(n - 1 + kPad));
-                    int ia = (int)std::min(a, 1e6), ic = (int)std::max(c, -1e6);
-                    if (ic - ia < 1) {
-                        if (ia >= n) { ia = n + kPad - 2; ic = n + kPad - 1; }
-                        else { ia = -kPad; ic = -kPad + 1; }
-                    }
-                    return std::make_pair(ia, ic - ia + 1);
-                };
-                const auto rr = clip(wlo / g.dw + row_c, whi / g.dw + row_c, rows);
                 auto cc = clip(amin / g.dalpha + col_c, amax / g.dalpha + col_c, cols);
                 // start the columns on a 16-byte boundary of the padded view row
                 const int shift = (cc.first + kPad) & 3;
                 cc.first -= shift;
                 cc.second += shift;
-                out[m].r0 = (int16_t)rr.first;
-                out[m].nr = (int16_t)rr.second;
-                out[m].c0 = (int16_t)cc.first;
-                out[m].nc = (int16_t)cc.second;
+                const double e = gr.z_first - g.z0 - P.h * lam;
+                for (int run = 0; run < P.bp_runs; ++run) {
+                    const double dz0 = e + (double)(run * P.bp_kz) * gr.dz;
+                    const double dz1 = e + (double)(run * P.bp_kz + P.bp_kz - 1) * gr.dz;
+                    const double wlo = g.D * dz0 / (dz0 >= 0 ? rmax : rmin);
+                    const double whi = g.D * dz1 / (dz1 >= 0 ? rmin : rmax);
+                    const auto rr = clip(wlo / g.dw + row_c, whi / g.dw + row_c, rows);
+                    BpBox &o = bx[((size_t)run * tiles + t) * P.W + m];
+                    o.r0 = (int16_t)rr.first;
+                    o.nr = (int16_t)rr.second;
+                    o.c0 = (int16_t)cc.first;
+                    o.nc = (int16_t)cc.second;
+                }
             }
         });
     }
