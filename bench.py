@@ -81,6 +81,60 @@ def cpu_baseline(wl, budget_views=None):
             "finite": bool(np.isfinite(f).all())}
 
 
+def serving_bench(n_requests=24, rate=20.0, budget=200e9):
+    """Serving workload (the serving recipe of synth.configs: grids 256^2x32 .. 512^2x160,
+    feed U[40,96] mm/turn, 2-10 turns, dense or 4x-sparse columns): the continuous-batching
+    server vs one-at-a-time katsevich_recon on the same Poisson trace and on the same
+    requests all arriving at once.  Plans are built first (their cold build time is
+    reported separately) so both sides measure the GPU serving path; sinograms are
+    generated into HBM before timing and copied device-to-device on admission."""
+    import numpy as np
+    import torch
+
+    from paper_2201_02309_amd import serve
+    from synth import configs, gpu_projector, phantom
+
+    dev = torch.device("cuda", 0)
+    wls = [configs.serving_request(i) for i in range(n_requests)]
+    sinos = []
+    for wl in wls:
+        g, gr = wl.geom.as_dict(), wl.grid.as_dict()
+        ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+        sinos.append(gpu_projector.project(ph, g, device=dev))
+    cache = serve.PlanCache(dev, workers=2)
+    t0 = time.perf_counter()
+    keys = [cache.request(wl.geom.as_dict(), wl.grid.as_dict())[0] for wl in wls]
+    for wl in wls:
+        cache.get_blocking(wl.geom.as_dict(), wl.grid.as_dict())
+    t_plans = time.perf_counter() - t0
+    builds = list(cache.build_seconds.values())
+    print(f"[bench] serving: {n_requests} plans built in {t_plans:.1f} s", file=sys.stderr,
+          flush=True)
+    out = {"workload": f"serving recipe, {n_requests} requests, Poisson {rate:g}/s and saturated",
+           "hbm_budget_bytes": budget, "warm_plans": True,
+           "plan_build_s_mean": float(np.mean(builds)), "plan_build_s_max": float(np.max(builds)),
+           "n_vv_total": int(sum(cache.plans[k].info["n_vv"] for k in keys))}
+    for name, saturated in (("poisson", False), ("saturated", True)):
+        arr = configs.serving_arrivals(n_requests, rate=rate, saturated=saturated)
+        mk = lambda: [serve.Request(rid=i, arrival=float(t), geom=wl.geom.as_dict(),
+                                    grid=wl.grid.as_dict(), sino=sinos[i])
+                      for i, (wl, t) in enumerate(zip(wls, arr))]
+        # warm the allocator / kernels once, untimed
+        serve.Server(cache, budget_bytes=budget).run(mk()[:4])
+        torch.cuda.synchronize()
+        srv = serve.Server(cache, budget_bytes=budget)
+        served = serve.summarize(srv.run(mk()))
+        torch.cuda.synchronize()
+        seq = serve.summarize(serve.serve_sequential(cache, mk()))
+        out[f"served_{name}"] = served
+        out[f"sequential_{name}"] = seq
+        print(f"[bench] serving {name}: served {served['volumes_per_s']:.1f} vol/s p99 "
+              f"{served['p99_latency_ms']:.1f} ms | sequential {seq['volumes_per_s']:.1f} vol/s "
+              f"p99 {seq['p99_latency_ms']:.1f} ms", file=sys.stderr, flush=True)
+    cache.close()
+    return out
+
+
 def _measured_traffic():
     """HBM bytes per backprojection launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (scaled by a plain-copy calibration), or None when the kernel or
@@ -104,6 +158,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests of the serving comparison (0 skips it)")
     ap.add_argument("--bp-slices", type=int, default=0,
                     help="slices per backprojection register run (0: library default)")
     args = ap.parse_args()
@@ -206,6 +262,11 @@ def main():
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
                      "flop_per_update": BP_FLOP_PER_UPDATE},
     }
+    if args.serve_requests > 0:
+        gF = ws = None
+        plan.release_workspace()
+        torch.cuda.empty_cache()
+        out["serving"] = serving_bench(args.serve_requests)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on one slice (cpu_baseline)", file=sys.stderr,
               flush=True)

@@ -167,6 +167,23 @@ int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF,
  * first pitch's tables): d_gF as written by katsevich_filter -> d_vol.  Asynchronous. */
 int katsevich_backproject(katsevich_plan_t plan, const float *d_gF, float *d_vol, void *stream);
 
+/* Size in bytes of the device queue buffer katsevich_backproject_batch needs for n plans
+ * (task descriptors and the work counter); 0 for n < 1. */
+uint64_t katsevich_batch_queue_bytes(int n_plans);
+
+/* Packed backprojection of n reconstructions in one persistent launch (serving): item i
+ * backprojects d_gF[i] (katsevich_filter output of plans[i]) into d_vol[i], exactly as
+ * katsevich_backproject would (bit-identical results).  Workgroups take (plan, pitch,
+ * slice run, tile) tasks from a device counter, so reconstructions of different sizes,
+ * pitches and grids share the GPU in one launch.  All plans must be bound and use the same
+ * bp_slices.  d_queue: caller device buffer of katsevich_batch_queue_bytes(n) bytes
+ * (256-byte aligned), overwritten; it must not be reused by another launch before this one
+ * has finished.  Asynchronous on stream.  Errors: KATS_EINVAL, KATS_ENOTBOUND,
+ * KATS_EWORKSPACE, KATS_EHIP. */
+int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *const *d_gF,
+                                float *const *d_vol, int n, void *d_queue, uint64_t queue_bytes,
+                                void *stream);
+
 /* Exact adjoint of katsevich_recon (transpose of the discrete operator): d_grad_vol
  * float32 [nz][ny][nx] -> d_grad_sino float32 [n_views][rows][cols] (overwritten).
  * d_ws: at least workspace_bytes.  Asynchronous on stream. */

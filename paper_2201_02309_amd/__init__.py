@@ -5,7 +5,8 @@ kernels + float64 host plan) declared in ``include/katsevich.h``; this package h
 that library's sources (``csrc/``), its build step and a thin ctypes binding.
 """
 from .katsevich import (Plan, KatsevichError, recon, recon_backward, filter_views,
-                        backproject, KatsevichFn, load_library, TABLES)
+                        backproject, backproject_batch, filtered_shape, KatsevichFn,
+                        load_library, TABLES)
 
 __all__ = ["Plan", "KatsevichError", "recon", "recon_backward", "filter_views", "backproject",
-           "KatsevichFn", "load_library", "TABLES"]
+           "backproject_batch", "filtered_shape", "KatsevichFn", "load_library", "TABLES"]

@@ -75,24 +75,32 @@ __device__ inline float lerp_bilinear(const float *t, int pitch_f, float tc, flo
     return fmaf(tr, bot - top, top);
 }
 
+// Shared memory of one backprojection workgroup.
+struct BpShared {
+    __attribute__((aligned(16))) float tile[2][kLMax];   // double-buffered footprint box
+    unsigned short words[4][kHull];  // per wave and view: active groups | full groups << 8
+    int red[8];
+};
+
+// One workgroup task: tile (bx, by) of the grid, slice run / pitch bz = pitch * runs + run.
+// Shared by the one-plan kernel (task = block index) and the packed multi-plan kernel.
 template <int KZ>
-__global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restrict__ gF,
-                                                float *__restrict__ vol,
-                                                const float4 *__restrict__ view_tab,
-                                                const uint2 *__restrict__ box_tab) {
+__device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__restrict__ vol,
+                        const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
+                        int bxi, int byi, int bz, BpShared &S) {
     static_assert(KZ % kKG == 0 && KZ / kKG <= 8, "groups use 8-bit masks");
     static_assert(kLR == 32, "box staging covers 32 rows with two 16-row passes");
     constexpr int NG = KZ / kKG;
-    __shared__ __attribute__((aligned(16))) float lds[2][kLMax];
-    __shared__ unsigned short words[4][kHull];  // per wave and view: active groups | full groups << 8
-    __shared__ int red[8];
+    auto &lds = S.tile;
+    auto &words = S.words;
+    auto &red = S.red;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int ix = blockIdx.x * kT + (tid & (kT - 1));
-    const int iy = blockIdx.y * kT + (tid >> 4);
-    const int pitch = blockIdx.z / p.runs;
-    const int run = blockIdx.z % p.runs;
+    const int ix = bxi * kT + (tid & (kT - 1));
+    const int iy = byi * kT + (tid >> 4);
+    const int pitch = bz / p.runs;
+    const int run = bz % p.runs;
     const int j0 = run * KZ;
     const int slices = min(p.ns, p.nz - pitch * p.ns);
     const int nrun = min(KZ, slices - j0);
@@ -168,7 +176,7 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
     const size_t vstride = (size_t)p.gf_rows * cpitch;
     // boxes read as two dwords (scalar loads) and unpacked: {r0 | nr << 16, c0 | nc << 16}
     const uint2 *__restrict__ boxes =
-        box_tab + ((size_t)(run * p.tiles_y + blockIdx.y) * p.tiles_x + blockIdx.x) * p.W;
+        box_tab + ((size_t)(run * p.tiles_y + byi) * p.tiles_x + bxi) * p.W;
     auto unpack = [](uint2 w) {
         BpBox b;
         b.r0 = (int16_t)(w.x & 0xffffu);
@@ -299,6 +307,69 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
     }
 }
 
+template <int KZ>
+__global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restrict__ gF,
+                                                float *__restrict__ vol,
+                                                const float4 *__restrict__ view_tab,
+                                                const uint2 *__restrict__ box_tab) {
+    __shared__ BpShared S;
+    bp_tile<KZ>(p, gF, vol, view_tab, box_tab, blockIdx.x, blockIdx.y, blockIdx.z, S);
+}
+
+// ---------------------------------------------------------------------------------
+// Packed backprojection of several plans in one persistent launch: every workgroup takes
+// the next task index from a device counter (one atomic per task), finds the request
+// owning it from the task prefix, and runs that request's tile.  The loop ends for every
+// workgroup once the counter passes the task count (no workgroup waits on another).
+// ---------------------------------------------------------------------------------
+struct BpRequest {
+    BpArgs a;
+    const float *gF;
+    float *vol;
+    const float4 *view;
+    const uint2 *boxes;
+    long long first_task;          // prefix of the task counts of earlier requests
+    long long n_tasks;
+};
+
+constexpr int kDescPerLaunch = 16;
+struct BpRequestChunk {
+    BpRequest r[kDescPerLaunch];
+    int n, offset;
+};
+
+// writes descriptors (kernel arguments are captured at launch) and clears the counter
+__global__ void k_write_requests(BpRequestChunk c, BpRequest *__restrict__ dst,
+                                 unsigned *__restrict__ counter) {
+    const int i = threadIdx.x;
+    if (i < c.n) dst[c.offset + i] = c.r[i];
+    if (c.offset == 0 && i == 0) *counter = 0u;
+}
+
+template <int KZ>
+__global__ __launch_bounds__(kNT) void k_bp_queue(const BpRequest *__restrict__ reqs, int n_req,
+                                                  long long n_tasks, unsigned *__restrict__ counter) {
+    __shared__ BpShared S;
+    __shared__ unsigned task_sh;
+    for (;;) {
+        if (threadIdx.x == 0) task_sh = atomicAdd(counter, 1u);
+        __syncthreads();
+        const long long task = (long long)__builtin_amdgcn_readfirstlane((int)task_sh);
+        __syncthreads();
+        if (task >= n_tasks) break;
+        int r = 0;
+        while (r + 1 < n_req && reqs[r + 1].first_task <= task) ++r;
+        const BpRequest &q = reqs[r];
+        long long local = task - q.first_task;
+        const int bxi = (int)(local % q.a.tiles_x);
+        local /= q.a.tiles_x;
+        const int byi = (int)(local % q.a.tiles_y);
+        const int bz = (int)(local / q.a.tiles_y);
+        bp_tile<KZ>(q.a, q.gF, q.vol, q.view, q.boxes, bxi, byi, bz, S);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Adjoint of the backprojection (the transpose of the operator above, acting on an
 // unpadded g^F cotangent).
@@ -389,8 +460,7 @@ __global__ __launch_bounds__(64) void k_backproject_T(KParams p, const float *__
 
 }  // namespace
 
-hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s) {
-    dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
+static BpArgs bp_args(const KParams &k) {
     BpArgs a;
     a.view = k.view;
     a.pi = k.pi;
@@ -422,13 +492,55 @@ hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hip
     a.gf_cols = k.gf_cols;
     a.atan_deg = k.atan_deg;
     for (int i = 0; i < 9; ++i) a.atan_coef[i] = k.atan_coef[i];
+    return a;
+}
+
+hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s) {
+    dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
+    const BpArgs a = bp_args(k);
+    const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
     switch (k.bp_kz) {
-        case 8: hipLaunchKernelGGL(k_bp_lds<8>, grid, dim3(kNT), 0, s, a, gF, vol, k.view,
-                                        reinterpret_cast<const uint2 *>(k.boxes)); break;
-        case 32: hipLaunchKernelGGL(k_bp_lds<32>, grid, dim3(kNT), 0, s, a, gF, vol, k.view,
-                                        reinterpret_cast<const uint2 *>(k.boxes)); break;
-        default: hipLaunchKernelGGL(k_bp_lds<16>, grid, dim3(kNT), 0, s, a, gF, vol, k.view,
-                                        reinterpret_cast<const uint2 *>(k.boxes)); break;
+        case 8: hipLaunchKernelGGL(k_bp_lds<8>, grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes); break;
+        case 32: hipLaunchKernelGGL(k_bp_lds<32>, grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes); break;
+        default: hipLaunchKernelGGL(k_bp_lds<16>, grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes); break;
+    }
+    return hipGetLastError();
+}
+
+uint64_t batch_queue_bytes(int n) {
+    return ((uint64_t)n * sizeof(BpRequest) + 255) / 256 * 256 + 256;
+}
+
+hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, float *const *vol,
+                                    int n, void *queue, int kz, int grid_limit, hipStream_t s) {
+    BpRequest *reqs = static_cast<BpRequest *>(queue);
+    unsigned *counter = reinterpret_cast<unsigned *>(static_cast<unsigned char *>(queue) +
+                                                     batch_queue_bytes(n) - 256);
+    long long total = 0;
+    for (int base = 0; base < n; base += kDescPerLaunch) {
+        BpRequestChunk c{};
+        c.offset = base;
+        c.n = n - base < kDescPerLaunch ? n - base : kDescPerLaunch;
+        for (int i = 0; i < c.n; ++i) {
+            const KParams &k = ks[base + i];
+            BpRequest &q = c.r[i];
+            q.a = bp_args(k);
+            q.gF = gF[base + i];
+            q.vol = vol[base + i];
+            q.view = k.view;
+            q.boxes = reinterpret_cast<const uint2 *>(k.boxes);
+            q.n_tasks = (long long)k.bp_tiles_x * k.bp_tiles_y * k.n_pitches * k.bp_runs;
+            q.first_task = total;
+            total += q.n_tasks;
+        }
+        hipLaunchKernelGGL(k_write_requests, dim3(1), dim3(64), 0, s, c, reqs, counter);
+    }
+    if (total == 0) return hipGetLastError();
+    const long long g = total < grid_limit ? total : grid_limit;
+    switch (kz) {
+        case 8: hipLaunchKernelGGL(k_bp_queue<8>, dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter); break;
+        case 32: hipLaunchKernelGGL(k_bp_queue<32>, dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter); break;
+        default: hipLaunchKernelGGL(k_bp_queue<16>, dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter); break;
     }
     return hipGetLastError();
 }

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/katsevich.h"
 #include "kernels.hpp"
@@ -300,6 +301,41 @@ int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, flo
     if (e == hipSuccess) e = kats::launch_backproject_T(k, d_grad_vol, g2, s);
     if (e == hipSuccess) e = kats::launch_filter_T(k, g2, g4, g2, d_grad_sino, s);
     if (e != hipSuccess) return hip_fail(e, "katsevich_recon_backward: launch");
+    return KATS_OK;
+}
+
+uint64_t katsevich_batch_queue_bytes(int n_plans) {
+    return n_plans > 0 ? kats::batch_queue_bytes(n_plans) : 0;
+}
+
+int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *const *d_gF,
+                                float *const *d_vol, int n, void *d_queue, uint64_t queue_bytes,
+                                void *stream) {
+    g_err.clear();
+    if (!plans || !d_gF || !d_vol || !d_queue || n < 1)
+        return fail(KATS_EINVAL, "katsevich_backproject_batch: null argument or n < 1");
+    if (queue_bytes < kats::batch_queue_bytes(n))
+        return fail(KATS_EWORKSPACE, "katsevich_backproject_batch: queue buffer too small");
+    if (!aligned256(d_queue)) return fail(KATS_EINVAL, "katsevich_backproject_batch: queue not 256-byte aligned");
+    std::vector<kats::KParams> ks((size_t)n);
+    int kz = -1;
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i] || !d_gF[i] || !d_vol[i])
+            return fail(KATS_EINVAL, "katsevich_backproject_batch: null plan or buffer at item " + std::to_string(i));
+        if (!plans[i]->P.d_tables)
+            return fail(KATS_ENOTBOUND, "katsevich_backproject_batch: plan " + std::to_string(i) + " not bound");
+        if (kz < 0) kz = plans[i]->P.bp_kz;
+        if (plans[i]->P.bp_kz != kz)
+            return fail(KATS_EINVAL, "katsevich_backproject_batch: plans use different bp_slices");
+        ks[(size_t)i] = kats::make_params(plans[i]->P);
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    hipError_t e = kats::launch_backproject_batch(ks.data(), d_gF, d_vol, n, d_queue, kz, 4 * cus,
+                                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_backproject_batch: launch");
     return KATS_OK;
 }
 

@@ -64,8 +64,9 @@ TABLES = {
 
 EXPORTED = ["katsevich_plan", "katsevich_plan_query", "katsevich_plan_bind",
             "katsevich_plan_export", "katsevich_recon", "katsevich_filter",
-            "katsevich_backproject", "katsevich_recon_backward", "katsevich_plan_destroy",
-            "katsevich_status_string", "katsevich_last_error"]
+            "katsevich_backproject", "katsevich_recon_backward", "katsevich_backproject_batch",
+            "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error",
+            "katsevich_batch_queue_bytes"]
 
 _lib = None
 
@@ -89,13 +90,18 @@ def load_library(path: str = LIB_PATH):
     lib.katsevich_backproject.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     lib.katsevich_recon_backward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_uint64,
                                              c_void_p]
+    lib.katsevich_backproject_batch.argtypes = [POINTER(c_void_p), POINTER(c_void_p),
+                                                POINTER(c_void_p), c_int, c_void_p, c_uint64,
+                                                c_void_p]
+    lib.katsevich_batch_queue_bytes.argtypes = [c_int]
+    lib.katsevich_batch_queue_bytes.restype = c_uint64
     lib.katsevich_plan_destroy.argtypes = [c_void_p]
     lib.katsevich_plan_destroy.restype = None
     lib.katsevich_status_string.argtypes = [c_int]
     lib.katsevich_status_string.restype = c_char_p
     lib.katsevich_last_error.argtypes = []
     lib.katsevich_last_error.restype = c_char_p
-    for name in EXPORTED[:8]:
+    for name in EXPORTED[:9]:
         getattr(lib, name).restype = c_int
     if path == LIB_PATH:
         _lib = lib
@@ -283,6 +289,33 @@ def backproject(plan: Plan, gF, out=None):
                                                       c_void_p(out.data_ptr()),
                                                       _stream_handle(gF.device)))
     return out
+
+
+def backproject_batch(plans, gFs, vols=None, queue=None):
+    """katsevich_backproject_batch: one persistent launch backprojecting every
+    (plans[i], gFs[i]) into vols[i] (allocated if None).  Returns the volumes."""
+    import torch
+    n = len(plans)
+    if n == 0:
+        return []
+    lib = plans[0]._lib
+    if vols is None:
+        vols = [torch.empty(_vol_shape(p), dtype=torch.float32, device=g.device)
+                for p, g in zip(plans, gFs)]
+    for p, g, v in zip(plans, gFs, vols):
+        _require(g, filtered_shape(p), "gF")
+        _require(v, _vol_shape(p), "vol")
+    need = int(lib.katsevich_batch_queue_bytes(n))
+    if queue is None or queue.numel() < need:
+        queue = torch.empty(need, dtype=torch.uint8, device=gFs[0].device)
+    arr = c_void_p * n
+    hp = arr(*[p.handle.value for p in plans])
+    hg = arr(*[g.data_ptr() for g in gFs])
+    hv = arr(*[v.data_ptr() for v in vols])
+    _check(lib, lib.katsevich_backproject_batch(hp, hg, hv, n, c_void_p(queue.data_ptr()),
+                                                c_uint64(queue.numel()),
+                                                _stream_handle(gFs[0].device)))
+    return vols
 
 
 def recon_backward(plan: Plan, grad_vol, out=None, ws=None):

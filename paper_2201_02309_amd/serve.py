@@ -1,0 +1,288 @@
+"""Continuous-batching reconstruction server on one GPU.
+
+Requests (a scan geometry, a voxel grid and a device-resident sinogram) arrive over time.
+The server
+
+* builds the float64 plan of each new geometry on host worker threads (plans are cached by
+  the exact geometry/grid tuple and bound to device tables once),
+* admits ready requests first-come-first-served while their device footprint (sinogram
+  copy, filter workspace, g^F, volume) fits the HBM budget, otherwise they wait until
+  earlier requests finish and free memory,
+* launches every admitted group as the per-request filter kernels followed by ONE packed
+  backprojection (``katsevich_backproject_batch``: a persistent launch whose workgroups
+  take tiles of all requests from a shared work queue), alternating between two streams so
+  a new group's filtering overlaps the previous group's backprojection,
+* records per-request latency (completion event time - arrival) and throughput.
+
+Every reconstruction step runs in libkatsevich; this module only schedules.  The packed
+launch computes each tile exactly as the one-request kernel does, so a request's volume is
+bit-identical alone and in the mix.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import katsevich as K
+
+
+def plan_key(geom: dict, grid: dict, n_psi: int = 0, bp_slices: int = 0):
+    return (tuple(sorted((k, float(v)) for k, v in geom.items())),
+            tuple(sorted((k, float(v)) for k, v in grid.items())), int(n_psi), int(bp_slices))
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float               # seconds after the trace start
+    geom: dict
+    grid: dict
+    sino: object                 # device tensor [n_views, rows, cols] (read only)
+    # filled by the server
+    t_plan_ready: float = float("nan")
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    cache_hit: bool = False
+    plan_seconds: float = 0.0
+    footprint: int = 0
+    volume: object = None
+
+    @property
+    def latency(self):
+        return self.t_done - self.arrival
+
+
+class PlanCache:
+    """Plans keyed by geometry; built and bound on worker threads (each worker binds on its
+    own stream, so the serving streams never wait for a table upload)."""
+
+    def __init__(self, device, workers=2, n_psi=0, bp_slices=0):
+        self.device = device
+        self.n_psi, self.bp_slices = n_psi, bp_slices
+        self.plans = {}
+        self.pending = {}
+        self.build_seconds = {}
+        self.hits = self.misses = 0
+        self.table_bytes = 0
+        self._lock = threading.Lock()
+        self._pool = ThreadPoolExecutor(max_workers=workers)
+        self._streams = {}
+
+    def _build(self, geom, grid):
+        import torch
+        t0 = time.perf_counter()
+        plan = K.Plan(geom, grid, n_psi=self.n_psi, bind=False, bp_slices=self.bp_slices)
+        tid = threading.get_ident()
+        with self._lock:
+            s = self._streams.get(tid)
+            if s is None:
+                s = self._streams[tid] = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(s):
+            plan.bind(self.device.index if hasattr(self.device, "index") else self.device)
+        return plan, time.perf_counter() - t0
+
+    def request(self, geom, grid):
+        """(key, cache_hit); starts a background build on a miss."""
+        key = plan_key(geom, grid, self.n_psi, self.bp_slices)
+        with self._lock:
+            if key in self.plans:
+                self.hits += 1
+                return key, True
+            self.misses += 1
+            if key not in self.pending:
+                self.pending[key] = self._pool.submit(self._build, geom, grid)
+            return key, False
+
+    def poll(self, key):
+        """Plan of key if built (moving it into the cache), else None."""
+        with self._lock:
+            if key in self.plans:
+                return self.plans[key]
+            fut = self.pending.get(key)
+        if fut is None or not fut.done():
+            return None
+        plan, secs = fut.result()
+        with self._lock:
+            if key not in self.plans:
+                self.plans[key] = plan
+                self.build_seconds[key] = secs
+                self.table_bytes += int(plan.info["table_bytes"])
+                self.pending.pop(key, None)
+            return self.plans[key]
+
+    def get_blocking(self, geom, grid):
+        key, _ = self.request(geom, grid)
+        while True:
+            p = self.poll(key)
+            if p is not None:
+                return p
+            time.sleep(0.0005)
+
+    def close(self):
+        self._pool.shutdown(wait=True)
+
+
+def footprint(plan: K.Plan) -> int:
+    """Device bytes a request holds while in flight."""
+    g = plan.geom
+    sino = int(g["n_views"]) * int(g["det_rows"]) * int(g["det_cols"]) * 4
+    gr = plan.grid
+    vol = int(gr["nx"]) * int(gr["ny"]) * int(gr["nz"]) * 4
+    return sino + int(plan.info["workspace_bytes_filter"]) + int(plan.info["filtered_bytes"]) + vol
+
+
+class Admission:
+    """First-come-first-served admission under a byte budget (pure policy)."""
+
+    def __init__(self, budget_bytes: int):
+        self.budget = int(budget_bytes)
+        self.used = 0
+
+    def try_admit(self, nbytes: int) -> bool:
+        if nbytes > self.budget:
+            raise ValueError(f"request footprint {nbytes} B exceeds the whole budget {self.budget} B")
+        if self.used + nbytes <= self.budget:
+            self.used += nbytes
+            return True
+        return False
+
+    def release(self, nbytes: int):
+        self.used -= nbytes
+        assert self.used >= 0
+
+
+class Server:
+    def __init__(self, plan_cache: PlanCache, budget_bytes: float = 200e9, max_batch: int = 32,
+                 keep_volumes: bool = False, n_streams: int = 2):
+        import torch
+        self.cache = plan_cache
+        self.device = plan_cache.device
+        self.admission = Admission(int(budget_bytes))
+        self.max_batch = max_batch
+        self.keep_volumes = keep_volumes
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.queues = [None] * n_streams
+
+    def _launch(self, si, batch):
+        import torch
+        s = self.streams[si]
+        plans, gFs, vols, held = [], [], [], []
+        with torch.cuda.stream(s):
+            for r, plan in batch:
+                sino = r.sino.clone()                      # D2D copy into the request's slot
+                ws = torch.empty(max(int(plan.info["workspace_bytes_filter"]), 256),
+                                 dtype=torch.uint8, device=self.device)
+                gF = K.filter_views(plan, sino, ws=ws)
+                vol = torch.empty(K._vol_shape(plan), dtype=torch.float32,
+                                  device=self.device)
+                plans.append(plan)
+                gFs.append(gF)
+                vols.append(vol)
+                held.append((sino, ws, gF))
+            need = int(plans[0]._lib.katsevich_batch_queue_bytes(len(plans)))
+            q = self.queues[si]
+            if q is None or q.numel() < need:
+                q = self.queues[si] = torch.empty(max(need, 4096), dtype=torch.uint8,
+                                                  device=self.device)
+            K.backproject_batch(plans, gFs, vols, queue=q)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ev, vols, held
+
+    def run(self, requests, clock_start=None):
+        """Serve requests (sorted by arrival); returns them with timings filled in."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = []                                   # arrived, plan maybe not ready
+        inflight = [None] * len(self.streams)          # (event, batch, vols, held)
+        t0 = time.perf_counter() if clock_start is None else clock_start
+        done = []
+        n = len(pending)
+        while len(done) < n:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                key, hit = self.cache.request(r.geom, r.grid)
+                r.cache_hit = hit
+                waiting.append((r, key))
+            # completions
+            for si, item in enumerate(inflight):
+                if item is not None and item[0].query():
+                    tdone = time.perf_counter() - t0
+                    _, batch, vols, held = item
+                    for (r, plan), v in zip(batch, vols):
+                        r.t_done = tdone
+                        r.volume = v if self.keep_volumes else None
+                        self.admission.release(r.footprint)
+                        done.append(r)
+                    inflight[si] = None
+            # admission into a free stream
+            free = [si for si, item in enumerate(inflight) if item is None]
+            launched = False
+            if free and waiting:
+                batch, rest = [], []
+                blocked = False
+                for r, key in waiting:
+                    plan = self.cache.poll(key)
+                    if plan is None:
+                        rest.append((r, key))
+                        continue
+                    if r.t_plan_ready != r.t_plan_ready:     # nan: first time seen ready
+                        r.t_plan_ready = time.perf_counter() - t0
+                        r.plan_seconds = self.cache.build_seconds.get(key, 0.0)
+                        r.footprint = footprint(plan)
+                    if not blocked and len(batch) < self.max_batch and \
+                            self.admission.try_admit(r.footprint):
+                        r.t_admit = time.perf_counter() - t0
+                        batch.append((r, plan))
+                    else:
+                        blocked = True                       # keep arrival order
+                        rest.append((r, key))
+                waiting = rest
+                if batch:
+                    si = free[0]
+                    ev, vols, held = self._launch(si, batch)
+                    inflight[si] = (ev, batch, vols, held)
+                    launched = True
+            if not launched:
+                time.sleep(0.0002)
+        return done
+
+
+def serve_sequential(plan_cache: PlanCache, requests, keep_volumes=False):
+    """Baseline: one request at a time in arrival order with the single-call
+    katsevich_recon (plan from the same cache, synchronised after every request)."""
+    import torch
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    t0 = time.perf_counter()
+    for r in reqs:
+        while time.perf_counter() - t0 < r.arrival:
+            time.sleep(0.0002)
+        key, hit = plan_cache.request(r.geom, r.grid)
+        r.cache_hit = hit
+        plan = plan_cache.get_blocking(r.geom, r.grid)
+        r.t_plan_ready = r.t_admit = time.perf_counter() - t0
+        r.plan_seconds = plan_cache.build_seconds.get(key, 0.0)
+        sino = r.sino.clone()
+        vol = K.recon(plan, sino)
+        torch.cuda.current_stream(sino.device).synchronize()
+        r.t_done = time.perf_counter() - t0
+        r.volume = vol if keep_volumes else None
+        del sino
+        plan.release_workspace()
+    return reqs
+
+
+def summarize(reqs):
+    lat = np.array([r.latency for r in reqs])
+    first = min(r.arrival for r in reqs)
+    last = max(r.t_done for r in reqs)
+    return {"requests": len(reqs), "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_latency_ms": float(lat.mean() * 1e3), "makespan_s": float(last - first),
+            "volumes_per_s": float(len(reqs) / max(last - first, 1e-9)),
+            "cache_hits": int(sum(r.cache_hit for r in reqs))}

@@ -22,6 +22,8 @@ the fan edge.  The z spacing divides the feed so that slices repeat every pitch.
 from __future__ import annotations
 
 import math
+
+import numpy as np
 from dataclasses import dataclass, field, asdict
 
 
@@ -191,3 +193,30 @@ def tiny(nxy=24, nz=16, cols=48, rows=8, views_per_turn=72, turns=3, feed=24.0,
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
+
+
+SERVING_GRIDS = ((256, 32, 1.4), (256, 96, 1.4), (512, 64, 0.7), (512, 160, 0.7))
+
+
+def serving_request(i: int) -> Workload:
+    """Request i of the serving workload, drawn with numpy default_rng(2000 + i): grid from
+    {256^2x32, 256^2x96 at 1.4 mm, 512^2x64, 512^2x160 at 0.7 mm}, feed U[40, 96] mm/turn,
+    2..10 turns, 736 or 184 (4x sparse) columns, 64 rows, 1160 views/turn; z spacing the
+    feed divided by round(feed / 1 mm) so that slices repeat every pitch."""
+    rng = np.random.default_rng(2000 + i)
+    nxy, nz, dxy = SERVING_GRIDS[int(rng.integers(0, len(SERVING_GRIDS)))]
+    feed = float(rng.uniform(40.0, 96.0))
+    turns = int(rng.integers(2, 11))
+    cols = 736 if rng.uniform() < 0.5 else 184
+    ns = max(1, int(round(feed / 1.0)))
+    return make_workload(f"serve-{i}", feed=feed, cols=cols, rows=64, views_per_turn=1160,
+                         turns=turns, nxy=nxy, nz=nz, dxy=dxy, slices_per_pitch=ns,
+                         phantom=_clinical_phantom(nxy, dxy, 12, 20), seed=2000 + i)
+
+
+def serving_arrivals(n: int, rate: float = 20.0, seed: int = 1004, saturated: bool = False):
+    """Poisson arrival times (seconds) of n requests at `rate` per second, or all at 0."""
+    if saturated:
+        return np.zeros(n)
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
