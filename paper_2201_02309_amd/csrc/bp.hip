@@ -42,16 +42,17 @@ __device__ inline float med3(float x, float lo, float hi) { return __builtin_amd
 // the other LDS buffer (one barrier per view).  Per (lane, view): v*, 1/v*, 1/rho and the
 // column coordinate (atan); per (lane, view, slice): the row coordinate (one FMA: rows
 // advance by dz D / (rho dw) per slice), two ds_read2 of the 2 x 2 taps, three lerps and
-// one FMA into the accumulator.  Before the view loop every wave classifies each view of
-// the hull into a 32-bit word (bit j: some voxel of slice j is active; bit 16+j: every
-// valid voxel of slice j has c_n = 1): inactive slices are skipped by a wave-uniform
-// branch and fully covered ones skip the coverage arithmetic.  Boxes larger than the LDS
-// tile read the same taps from the zero-padded g^F in HBM instead.
+// one FMA into the accumulator.  Slices are handled in groups of kKG: before the view
+// loop every wave classifies each view of the hull into a 16-bit word (bit g: some voxel
+// of group g is active; bit 8+g: every valid voxel of group g has c_n = 1): inactive
+// groups are skipped by a wave-uniform branch and fully covered ones skip the coverage
+// arithmetic.  When the plan has boxes larger than the LDS tile, the kernel instance with
+// the fallback reads those views' taps from the zero-padded g^F in HBM instead.
 // ---------------------------------------------------------------------------------
 constexpr int kT = kBpTile;       // 16
 constexpr int kNT = kT * kT;      // 256 lanes
-constexpr int kLP = 64;           // LDS tile row pitch (floats) = max box columns
-constexpr int kLR = 32;           // max box rows
+constexpr int kLP = kBpBoxCols;   // LDS tile row pitch (floats) = max box columns
+constexpr int kLR = kBpBoxRows;   // max box rows
 constexpr int kLMax = kLP * kLR;  // 2048 floats per buffer
 constexpr int kHull = 2048;       // max views of a workgroup hull with per-view group words
 constexpr int kKG = 4;            // slices per branch group
@@ -84,7 +85,9 @@ struct BpShared {
 
 // One workgroup task: tile (bx, by) of the grid, slice run / pitch bz = pitch * runs + run.
 // Shared by the one-plan kernel (task = block index) and the packed multi-plan kernel.
-template <int KZ>
+// FB: some box of the plan may exceed the LDS tile (those views read their taps from HBM);
+// without it the view loop has a single path, which keeps the accumulators in place.
+template <int KZ, bool FB>
 __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__restrict__ vol,
                         const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
                         int bxi, int byi, int bz, BpShared &S) {
@@ -187,7 +190,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
     };
     // g^F of pitch-relative view 0; element (0, 0) of a view is detector cell (-kPad, -kPad)
     const float *gF0 = gF + (size_t)(base - p.first_view) * vstride;
-    auto fits = [](const BpBox &b) { return b.nr <= kLR && b.nc <= kLP; };
+    auto fits = [](const BpBox &b) { return !FB || (b.nr <= kLR && b.nc <= kLP); };
 
     // Box staging: 16 lanes per LDS row, one aligned float4 each (the plan starts every box
     // on a 16-byte boundary of the padded row; columns past the box land in unused LDS).
@@ -238,9 +241,16 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
         if (p.atan_deg >= 0) {
             const float t = u * vinv;                        // tan(alpha*)
             const float s2 = t * t;
-            float qa = p.atan_coef[8];
+            float qa;
+            if (p.atan_deg <= 4) {                           // uniform: the plan's degree
+                qa = p.atan_coef[4];
 #pragma unroll
-            for (int k = 7; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
+                for (int k = 3; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
+            } else {
+                qa = p.atan_coef[8];
+#pragma unroll
+                for (int k = 7; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
+            }
             acol = t * qa;
         } else {
             acol = atan2f(u, v) * p.inv_dalpha;
@@ -265,17 +275,17 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
                 const int r0 = (int)rr;               // rr >= 0: truncation = floor
                 val[s] = lerp_bilinear(T + r0 * tp, tp, tc, __builtin_amdgcn_fractf(rr));
             }
-            if (word & (1u << (8 + g))) {
-#pragma unroll
-                for (int s = 0; s < kKG; ++s) acc[g * kKG + s] = fmaf(vinv, val[s], acc[g * kKG + s]);
-            } else {
+            // the coverage weight scales the taps in place, so that both paths end in
+            // the same FMA on the accumulators
+            if (!(word & (1u << (8 + g)))) {
 #pragma unroll
                 for (int s = 0; s < kKG; ++s) {
                     const int jj = g * kKG + s;
-                    const float cw = med3(fminf(mf - A[jj], B[jj] - mf), 0.0f, 1.0f);
-                    acc[jj] = fmaf(cw * vinv, val[s], acc[jj]);
+                    val[s] *= med3(fminf(mf - A[jj], B[jj] - mf), 0.0f, 1.0f);
                 }
             }
+#pragma unroll
+            for (int s = 0; s < kKG; ++s) acc[g * kKG + s] = fmaf(vinv, val[s], acc[g * kKG + s]);
         };
         if (fits(b)) {
             const float *T = &lds[buf][c0];
@@ -307,13 +317,13 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
     }
 }
 
-template <int KZ>
+template <int KZ, bool FB>
 __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restrict__ gF,
                                                 float *__restrict__ vol,
                                                 const float4 *__restrict__ view_tab,
                                                 const uint2 *__restrict__ box_tab) {
     __shared__ BpShared S;
-    bp_tile<KZ>(p, gF, vol, view_tab, box_tab, blockIdx.x, blockIdx.y, blockIdx.z, S);
+    bp_tile<KZ, FB>(p, gF, vol, view_tab, box_tab, blockIdx.x, blockIdx.y, blockIdx.z, S);
 }
 
 // ---------------------------------------------------------------------------------
@@ -346,7 +356,7 @@ __global__ void k_write_requests(BpRequestChunk c, BpRequest *__restrict__ dst,
     if (c.offset == 0 && i == 0) *counter = 0u;
 }
 
-template <int KZ>
+template <int KZ, bool FB>
 __global__ __launch_bounds__(kNT) void k_bp_queue(const BpRequest *__restrict__ reqs, int n_req,
                                                   long long n_tasks, unsigned *__restrict__ counter) {
     __shared__ BpShared S;
@@ -365,7 +375,7 @@ __global__ __launch_bounds__(kNT) void k_bp_queue(const BpRequest *__restrict__ 
         local /= q.a.tiles_x;
         const int byi = (int)(local % q.a.tiles_y);
         const int bz = (int)(local / q.a.tiles_y);
-        bp_tile<KZ>(q.a, q.gF, q.vol, q.view, q.boxes, bxi, byi, bz, S);
+        bp_tile<KZ, FB>(q.a, q.gF, q.vol, q.view, q.boxes, bxi, byi, bz, S);
         __syncthreads();
     }
 }
@@ -499,11 +509,15 @@ hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hip
     dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
     const BpArgs a = bp_args(k);
     const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
+#define KATS_BP_LAUNCH(KZ, FB) \
+    hipLaunchKernelGGL((k_bp_lds<KZ, FB>), grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes)
+    const bool fb = !k.bp_all_fit;
     switch (k.bp_kz) {
-        case 8: hipLaunchKernelGGL(k_bp_lds<8>, grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes); break;
-        case 32: hipLaunchKernelGGL(k_bp_lds<32>, grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes); break;
-        default: hipLaunchKernelGGL(k_bp_lds<16>, grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes); break;
+        case 8: if (fb) KATS_BP_LAUNCH(8, true); else KATS_BP_LAUNCH(8, false); break;
+        case 32: if (fb) KATS_BP_LAUNCH(32, true); else KATS_BP_LAUNCH(32, false); break;
+        default: if (fb) KATS_BP_LAUNCH(16, true); else KATS_BP_LAUNCH(16, false); break;
     }
+#undef KATS_BP_LAUNCH
     return hipGetLastError();
 }
 
@@ -517,6 +531,8 @@ hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, f
     unsigned *counter = reinterpret_cast<unsigned *>(static_cast<unsigned char *>(queue) +
                                                      batch_queue_bytes(n) - 256);
     long long total = 0;
+    bool fb = false;
+    for (int i = 0; i < n; ++i) fb = fb || !ks[i].bp_all_fit;
     for (int base = 0; base < n; base += kDescPerLaunch) {
         BpRequestChunk c{};
         c.offset = base;
@@ -537,11 +553,14 @@ hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, f
     }
     if (total == 0) return hipGetLastError();
     const long long g = total < grid_limit ? total : grid_limit;
+#define KATS_BPQ_LAUNCH(KZ, FB) \
+    hipLaunchKernelGGL((k_bp_queue<KZ, FB>), dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter)
     switch (kz) {
-        case 8: hipLaunchKernelGGL(k_bp_queue<8>, dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter); break;
-        case 32: hipLaunchKernelGGL(k_bp_queue<32>, dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter); break;
-        default: hipLaunchKernelGGL(k_bp_queue<16>, dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter); break;
+        case 8: if (fb) KATS_BPQ_LAUNCH(8, true); else KATS_BPQ_LAUNCH(8, false); break;
+        case 32: if (fb) KATS_BPQ_LAUNCH(32, true); else KATS_BPQ_LAUNCH(32, false); break;
+        default: if (fb) KATS_BPQ_LAUNCH(16, true); else KATS_BPQ_LAUNCH(16, false); break;
     }
+#undef KATS_BPQ_LAUNCH
     return hipGetLastError();
 }
 

@@ -1,8 +1,8 @@
 // Filtering kernels of the Katsevich reconstruction for gfx950 (Sec. II steps 1-6):
 //   k_deriv_lw    derivative at constant direction (eq. Deriv) + length weighting (eq. LW)
-//   k_fr_hilbert  forward height rebinning onto two kappa-lines (eqs. FR, w_k) packed as one
+//   k_hilbert_fft forward height rebinning onto two kappa-lines (eqs. FR, w_k) packed as one
 //                 complex row, then the Hilbert transform in alpha (eq. HF, kernel of e4) as a
-//                 zero-padded linear convolution by LDS Stockham FFTs
+//                 zero-padded linear convolution by register Stockham FFTs
 //   k_br_cos      backward height rebinning (eq. BR) + post-cosine weighting (eq. PW)
 // All kernels are HBM-streaming: one pass over their input and output, coalesced along
 // detector columns.
@@ -38,112 +38,261 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_lw(KParams p, const floa
 __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
+// times -i (forward transform) or +i (inverse)
+template <bool INV>
+__device__ inline float2 rot(float2 a) { return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x); }
 
-// Stockham autosort FFT of length N = 2^log2n in LDS (radix-2 first pass when log2n is
-// odd, then radix-4).  X holds the input; returns the buffer holding the output.
-// tw[k] = exp(-2 pi i k / N); the inverse uses conjugate twiddles and +i rotations
-// (no 1/N: that factor is folded into the Hilbert spectrum).
-template <bool kInverse>
-__device__ float2 *fft_lds(float2 *X, float2 *Y, const float2 *tw, int N, int log2n) {
-    const int tid = threadIdx.x;
-    int p = 1;
-    if (log2n & 1) {
-        const int half = N >> 1;
-        for (int i = tid; i < half; i += kFftThreads) {
-            const int k = i & (p - 1);
-            float2 w = tw[k * (N / (2 * p))];
-            if (kInverse) w.y = -w.y;
-            const float2 u0 = X[i];
-            const float2 u1 = cmul(X[i + half], w);
-            const int j = ((i - k) << 1) + k;
-            Y[j] = make_float2(u0.x + u1.x, u0.y + u1.y);
-            Y[j + p] = make_float2(u0.x - u1.x, u0.y - u1.y);
-        }
-        __syncthreads();
-        float2 *t = X; X = Y; Y = t;
-        p = 2;
-    }
-    const int q = N >> 2;
-    while (p < N) {
-        const int s = N / (4 * p);
-        for (int i = tid; i < q; i += kFftThreads) {
-            const int k = i & (p - 1);
-            float2 w1 = tw[k * s], w2 = tw[2 * k * s], w3 = tw[3 * k * s];
-            if (kInverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
-            const float2 u0 = X[i];
-            const float2 u1 = cmul(X[i + q], w1);
-            const float2 u2 = cmul(X[i + 2 * q], w2);
-            const float2 u3 = cmul(X[i + 3 * q], w3);
-            const float2 a0 = make_float2(u0.x + u2.x, u0.y + u2.y);
-            const float2 a1 = make_float2(u0.x - u2.x, u0.y - u2.y);
-            const float2 a2 = make_float2(u1.x + u3.x, u1.y + u3.y);
-            const float2 d = make_float2(u1.x - u3.x, u1.y - u3.y);
-            const float2 a3 = kInverse ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
-            const int j = ((i - k) << 2) + k;
-            Y[j] = make_float2(a0.x + a2.x, a0.y + a2.y);
-            Y[j + p] = make_float2(a1.x + a3.x, a1.y + a3.y);
-            Y[j + 2 * p] = make_float2(a0.x - a2.x, a0.y - a2.y);
-            Y[j + 3 * p] = make_float2(a1.x - a3.x, a1.y - a3.y);
-        }
-        __syncthreads();
-        float2 *t = X; X = Y; Y = t;
-        p <<= 2;
-    }
-    return X;
+// ---------------------------------------------------------------------------------
+// Hilbert filtering along detector columns (eq. HF) as a zero-padded linear convolution:
+// y = IDFT_N(i Im[K^](f) / N * DFT_N(x)), N = fft_len >= 2 cols - 1 (a power of two).
+// Two real kappa rows are transformed together as one complex row (real and imaginary
+// parts); the kernel spectrum is purely imaginary (odd kernel), so the two stay separate.
+//
+// Each transform is spread over T = N / 16 threads holding 16 complex values in
+// registers.  Stockham radix passes: a radix-R pass of span L maps butterfly i
+// (k = i mod L) with inputs x[i + j N/R] (times w_{RL}^{jk}) to outputs at
+// (i - k) R + k + m L.  Forward: one radix-RF pass (RF = N / 16^q in {2, 4, 8}, or 16)
+// reading the rebinned input straight from global memory, then radix-16 passes; the
+// last leaves X[t + m T] in thread t, which is exactly the input distribution of the
+// inverse's first radix-16 pass, so the spectrum product needs no exchange.  Inverse:
+// radix-16 passes of span 1, 16, ..., then the radix-RF pass writing the result to global
+// memory.  Passes exchange through LDS with the bijective swizzle x ^ ((x >> 4) & 31)
+// (the exchange patterns are free of bank conflicts up to two-way).  Twiddles are the
+// plan's exp(-2 pi i n / N) table, read through the cache.
+// ---------------------------------------------------------------------------------
+template <bool INV>
+__device__ inline void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
+    const float2 s0 = cadd(a0, a2), d0 = csub(a0, a2);
+    const float2 s1 = cadd(a1, a3), d1 = rot<INV>(csub(a1, a3));
+    a0 = cadd(s0, s1);
+    a2 = csub(s0, s1);
+    a1 = cadd(d0, d1);
+    a3 = csub(d0, d1);
 }
 
-// One block = one filtered view x one pair of kappa-lines (k_a = 2*pair, k_b = k_a + 1).
-__global__ __launch_bounds__(kFftThreads) void k_fr_hilbert(KParams p, const float *__restrict__ g2,
-                                                            float *__restrict__ g4) {
-    extern __shared__ float2 lds[];
-    const int N = p.fft_len;
-    float2 *bufA = lds;
-    float2 *bufB = lds + N;
-    float2 *tw = lds + 2 * N;
-    const int n_pairs = (p.n_psi + 1) >> 1;
-    const long long i = blockIdx.x / n_pairs;
-    const int ka = 2 * (int)(blockIdx.x % n_pairs);
-    const int kb = ka + 1;
-    const bool has_b = kb < p.n_psi;
+// w_16^e (forward) or its conjugate, e in 0..9 known at compile time
+template <bool INV>
+__device__ inline float2 tw16(float2 v, int e) {
+    constexpr float c1 = 0.923879532511286756f, s1 = 0.382683432365089772f;
+    constexpr float r2 = 0.707106781186547524f;
+    float c = 1.0f, s = 0.0f;           // w = c - i s  (forward)
+    switch (e) {
+        case 0: return v;
+        case 4: return rot<INV>(v);
+        case 1: c = c1; s = s1; break;
+        case 2: c = r2; s = r2; break;
+        case 3: c = s1; s = c1; break;
+        case 6: c = -r2; s = r2; break;
+        case 9: c = -c1; s = -s1; break;
+        default: break;
+    }
+    return cmul(v, make_float2(c, INV ? s : -s));
+}
+
+// In-place DFT of v[0..R-1] in natural order, R in {2, 4, 8, 16}.
+template <int R, bool INV>
+__device__ inline void dft(float2 *v) {
+    if constexpr (R == 2) {
+        const float2 a = v[0];
+        v[0] = cadd(a, v[1]);
+        v[1] = csub(a, v[1]);
+    } else if constexpr (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 8) {
+        // index j = 2 j1 + j2, m = m1 + 4 m2
+        float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<INV>(e0, e1, e2, e3);
+        dft4<INV>(o0, o1, o2, o3);
+        o1 = tw16<INV>(o1, 2);          // w_8^1 = w_16^2
+        o2 = tw16<INV>(o2, 4);          // w_8^2 = w_16^4
+        o3 = tw16<INV>(o3, 6);          // w_8^3 = w_16^6
+        v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+        v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+        v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+        v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+    } else {
+        static_assert(R == 16, "radix");
+        // index j = 4 j1 + j2, m = m1 + 4 m2: DFT4 over j1, twiddle w_16^(j2 m1), DFT4 over j2
+#pragma unroll
+        for (int j2 = 0; j2 < 4; ++j2) dft4<INV>(v[j2], v[4 + j2], v[8 + j2], v[12 + j2]);
+#pragma unroll
+        for (int j2 = 1; j2 < 4; ++j2)
+#pragma unroll
+            for (int m1 = 1; m1 < 4; ++m1) v[j2 + 4 * m1] = tw16<INV>(v[j2 + 4 * m1], j2 * m1);
+#pragma unroll
+        for (int m1 = 0; m1 < 4; ++m1) dft4<INV>(v[4 * m1], v[4 * m1 + 1], v[4 * m1 + 2], v[4 * m1 + 3]);
+        // y[m1 + 4 m2] now sits in v[4 m1 + m2]: transpose the 4 x 4 index
+        float2 t[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) t[m] = v[4 * (m & 3) + (m >> 2)];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = t[m];
+    }
+}
+
+__device__ inline int fft_swz(int x) { return x ^ ((x >> 4) & 31); }
+
+template <int LOG2N>
+struct FftShape {
+    static constexpr int N = 1 << LOG2N;
+    static constexpr int T = N / 16;                                   // threads per transform
+    static constexpr int RF = (LOG2N % 4) ? (1 << (LOG2N % 4)) : 16;   // edge pass radix
+    static constexpr int NP16 = (LOG2N - ((LOG2N % 4) ? (LOG2N % 4) : 4)) / 4;
+    static constexpr int F = kFftThreads / T;                          // transforms per block
+    static_assert(LOG2N >= 6 && LOG2N <= 11, "fft length 64 .. 2048");
+};
+
+// A middle radix-16 pass of span L on this thread's butterfly i = t: twiddles then DFT.
+template <int LOG2N, bool INV>
+__device__ inline void pass16(float2 *v, int t, int L, const float2 *__restrict__ tw) {
+    constexpr int N = FftShape<LOG2N>::N;
+    const int k = t % L;
+    const int step = k * (N / (16 * L));
+#pragma unroll
+    for (int j = 1; j < 16; ++j) {
+        const float2 w = tw[j * step];
+        v[j] = cmul(v[j], INV ? conj2(w) : w);
+    }
+    dft<16, INV>(v);
+}
+
+// Filter (ADJ = false): rebin kappa rows ka, kb from g2, convolve, write g4.
+// Adjoint Hilbert (ADJ = true): rows ka, kb of g4bar convolved with the negated spectrum
+// (H^T = -H), in place.
+template <int LOG2N, bool ADJ>
+__global__ __launch_bounds__(kFftThreads) void k_hilbert_fft(KParams p, const float *__restrict__ g2,
+                                                             float *__restrict__ g4) {
+    using S = FftShape<LOG2N>;
+    constexpr int N = S::N, T = S::T, RF = S::RF, NB = 16 / RF;
+    __shared__ float2 lds[S::F * N];
     const int tid = threadIdx.x;
-    for (int k = tid; k < N; k += kFftThreads) tw[k] = p.twiddle[k];
-    const float *v2 = g2 + (size_t)i * p.rows * p.cols;
-    for (int c = tid; c < N; c += kFftThreads) {
-        float a = 0.0f, b = 0.0f;
-        if (c < p.cols) {
-            {
-                const int r0 = p.fr_row[ka * p.cols + c];
-                const float t = p.fr_w[ka * p.cols + c];
-                const float x0 = (r0 >= 0 && r0 < p.rows) ? v2[r0 * p.cols + c] : 0.0f;
-                const float x1 = (r0 + 1 >= 0 && r0 + 1 < p.rows) ? v2[(r0 + 1) * p.cols + c] : 0.0f;
-                a = (1.0f - t) * x0 + t * x1;
+    const int t = tid % T;
+    float2 *X = lds + (tid / T) * N;
+    const int n_pairs = (p.n_psi + 1) >> 1;
+    const long long xf = (long long)blockIdx.x * S::F + tid / T;     // transform index
+    const bool live = xf < (long long)p.n_filt * n_pairs;
+    const long long i = live ? xf / n_pairs : 0;
+    const int ka = live ? 2 * (int)(xf % n_pairs) : 0;
+    const int kb = ka + 1;
+    const bool has_b = live && kb < p.n_psi;
+    const int cols = p.cols, rows = p.rows;
+    const float2 *__restrict__ tw = p.twiddle;
+    float *row = g4 + (size_t)i * p.n_psi * cols;                     // output / in-place rows
+    const float *v2 = g2 + (size_t)i * rows * cols;
+    auto rebin = [&](int k, int c) -> float {
+        const int r0 = p.fr_row[k * cols + c];
+        const float w = p.fr_w[k * cols + c];
+        const float x0 = (r0 >= 0 && r0 < rows) ? v2[r0 * cols + c] : 0.0f;
+        const float x1 = (r0 + 1 >= 0 && r0 + 1 < rows) ? v2[(r0 + 1) * cols + c] : 0.0f;
+        return (1.0f - w) * x0 + w * x1;
+    };
+    float2 v[16];
+    // forward edge pass (span 1): butterflies i = t + T b, inputs x[i + j N/RF]
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int j = 0; j < RF; ++j) {
+            const int c = t + T * b + j * (N / RF);
+            float a = 0.0f, bb = 0.0f;
+            if (live && c < cols) {
+                if constexpr (ADJ) {
+                    a = row[ka * cols + c];
+                    if (has_b) bb = row[kb * cols + c];
+                } else {
+                    a = rebin(ka, c);
+                    if (has_b) bb = rebin(kb, c);
+                }
             }
-            if (has_b) {
-                const int r0 = p.fr_row[kb * p.cols + c];
-                const float t = p.fr_w[kb * p.cols + c];
-                const float x0 = (r0 >= 0 && r0 < p.rows) ? v2[r0 * p.cols + c] : 0.0f;
-                const float x1 = (r0 + 1 >= 0 && r0 + 1 < p.rows) ? v2[(r0 + 1) * p.cols + c] : 0.0f;
-                b = (1.0f - t) * x0 + t * x1;
+            v[b * RF + j] = make_float2(a, bb);
+        }
+        dft<RF, false>(v + b * RF);
+#pragma unroll
+        for (int m = 0; m < RF; ++m) X[fft_swz((t + T * b) * RF + m)] = v[b * RF + m];
+    }
+    __syncthreads();
+    // forward radix-16 passes, span L = RF, 16 RF, ...; the last keeps X[t + m T]
+    int L = RF;
+#pragma unroll
+    for (int q = 0; q < S::NP16; ++q) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = X[fft_swz(t + j * T)];
+        pass16<LOG2N, false>(v, t, L, tw);
+        if (q + 1 < S::NP16) {
+            __syncthreads();
+            const int k = t % L;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) X[fft_swz((t - k) * 16 + k + m * L)] = v[m];
+            __syncthreads();
+        }
+        L *= 16;
+    }
+    // spectrum: i * Im[K^](f) / N (negated for the adjoint), f = t + m T
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const float kim = ADJ ? -p.hil_im[t + m * T] : p.hil_im[t + m * T];
+        v[m] = make_float2(-v[m].y * kim, v[m].x * kim);
+    }
+    // inverse radix-16 passes, span 1, 16, ...; the first starts from registers
+    L = 1;
+#pragma unroll
+    for (int q = 0; q < S::NP16; ++q) {
+        if (q > 0) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = X[fft_swz(t + j * T)];
+            pass16<LOG2N, true>(v, t, L, tw);
+        } else {
+            dft<16, true>(v);
+        }
+        __syncthreads();
+        const int k = t % L;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) X[fft_swz((t - k) * 16 + k + m * L)] = v[m];
+        __syncthreads();
+        L *= 16;
+    }
+    // inverse edge pass, span N / RF: butterfly i = t + T b writes y[i + m N/RF]
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int ib = t + T * b;
+#pragma unroll
+        for (int j = 0; j < RF; ++j) {
+            float2 x = X[fft_swz(ib + j * (N / RF))];
+            if (j > 0) x = cmul(x, conj2(tw[j * ib * (N / (RF * L))]));
+            v[b * RF + j] = x;
+        }
+        dft<RF, true>(v + b * RF);
+        if (live) {
+#pragma unroll
+            for (int m = 0; m < RF; ++m) {
+                const int c = ib + m * (N / RF);
+                if (c < cols) {
+                    row[ka * cols + c] = v[b * RF + m].x;
+                    if (has_b) row[kb * cols + c] = v[b * RF + m].y;
+                }
             }
         }
-        bufA[c] = make_float2(a, b);
     }
-    __syncthreads();
-    float2 *Z = fft_lds<false>(bufA, bufB, tw, N, p.log2n);
-    float2 *other = (Z == bufA) ? bufB : bufA;
-    // multiply by the purely imaginary kernel spectrum i * Im[f] (1/N folded in)
-    for (int f = tid; f < N; f += kFftThreads) {
-        const float kim = p.hil_im[f];
-        const float2 z = Z[f];
-        Z[f] = make_float2(-z.y * kim, z.x * kim);
-    }
-    __syncthreads();
-    float2 *Y = fft_lds<true>(Z, other, tw, N, p.log2n);
-    float *out = g4 + (size_t)i * p.n_psi * p.cols;
-    for (int c = tid; c < p.cols; c += kFftThreads) {
-        const float2 y = Y[c];
-        out[ka * p.cols + c] = y.x;
-        if (has_b) out[kb * p.cols + c] = y.y;
+}
+
+template <bool ADJ>
+void launch_hilbert(const KParams &k, const float *g2, float *g4, hipStream_t s) {
+    const int n_pairs = (k.n_psi + 1) / 2;
+    const long long nt = (long long)k.n_filt * n_pairs;
+    auto blocks = [&](int log2n) {
+        const int f = kFftThreads / ((1 << log2n) / 16);
+        return dim3((unsigned)((nt + f - 1) / f));
+    };
+    switch (k.log2n) {
+        case 6: hipLaunchKernelGGL((k_hilbert_fft<6, ADJ>), blocks(6), dim3(kFftThreads), 0, s, k, g2, g4); break;
+        case 7: hipLaunchKernelGGL((k_hilbert_fft<7, ADJ>), blocks(7), dim3(kFftThreads), 0, s, k, g2, g4); break;
+        case 8: hipLaunchKernelGGL((k_hilbert_fft<8, ADJ>), blocks(8), dim3(kFftThreads), 0, s, k, g2, g4); break;
+        case 9: hipLaunchKernelGGL((k_hilbert_fft<9, ADJ>), blocks(9), dim3(kFftThreads), 0, s, k, g2, g4); break;
+        case 10: hipLaunchKernelGGL((k_hilbert_fft<10, ADJ>), blocks(10), dim3(kFftThreads), 0, s, k, g2, g4); break;
+        default: hipLaunchKernelGGL((k_hilbert_fft<11, ADJ>), blocks(11), dim3(kFftThreads), 0, s, k, g2, g4); break;
     }
 }
 
@@ -190,48 +339,6 @@ __global__ __launch_bounds__(kElemThreads) void k_br_cos_T(KParams p, const floa
         const float v = ca * src[e];
         dst[k0 * p.cols + c] += (1.0f - t) * v;
         dst[(k0 + 1) * p.cols + c] += t * v;
-    }
-}
-
-// H^T = -H: the same FFT convolution with the negated spectrum, then FR^T (scatter of the
-// two kappa rows into detector rows is done by k_fr_T below, so this kernel only writes
-// g3bar in place of g4bar).
-__global__ __launch_bounds__(kFftThreads) void k_hilbert_T(KParams p, float *__restrict__ g4bar) {
-    extern __shared__ float2 lds[];
-    const int N = p.fft_len;
-    float2 *bufA = lds;
-    float2 *bufB = lds + N;
-    float2 *tw = lds + 2 * N;
-    const int n_pairs = (p.n_psi + 1) >> 1;
-    const long long i = blockIdx.x / n_pairs;
-    const int ka = 2 * (int)(blockIdx.x % n_pairs);
-    const int kb = ka + 1;
-    const bool has_b = kb < p.n_psi;
-    const int tid = threadIdx.x;
-    for (int k = tid; k < N; k += kFftThreads) tw[k] = p.twiddle[k];
-    float *row = g4bar + (size_t)i * p.n_psi * p.cols;
-    for (int c = tid; c < N; c += kFftThreads) {
-        float a = 0.0f, b = 0.0f;
-        if (c < p.cols) {
-            a = row[ka * p.cols + c];
-            if (has_b) b = row[kb * p.cols + c];
-        }
-        bufA[c] = make_float2(a, b);
-    }
-    __syncthreads();
-    float2 *Z = fft_lds<false>(bufA, bufB, tw, N, p.log2n);
-    float2 *other = (Z == bufA) ? bufB : bufA;
-    for (int f = tid; f < N; f += kFftThreads) {
-        const float kim = -p.hil_im[f];
-        const float2 z = Z[f];
-        Z[f] = make_float2(-z.y * kim, z.x * kim);
-    }
-    __syncthreads();
-    float2 *Y = fft_lds<true>(Z, other, tw, N, p.log2n);
-    for (int c = tid; c < p.cols; c += kFftThreads) {
-        const float2 y = Y[c];
-        row[ka * p.cols + c] = y.x;
-        if (has_b) row[kb * p.cols + c] = y.y;
     }
 }
 
@@ -283,10 +390,7 @@ hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *
     const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
     hipLaunchKernelGGL(k_deriv_lw, dim3((unsigned)k.n_filt, k.rows, cb), dim3(kElemThreads), 0, s,
                        k, sino, g2);
-    const int n_pairs = (k.n_psi + 1) / 2;
-    const size_t lds = (size_t)3 * k.fft_len * sizeof(float2);
-    hipLaunchKernelGGL(k_fr_hilbert, dim3((unsigned)(k.n_filt * n_pairs)), dim3(kFftThreads), lds, s,
-                       k, g2, g4);
+    launch_hilbert<false>(k, g2, g4, s);
     const int cbp = (k.gf_cols + kElemThreads - 1) / kElemThreads;
     hipLaunchKernelGGL(k_br_cos, dim3((unsigned)k.n_filt, k.gf_rows, cbp), dim3(kElemThreads),
                        0, s, k, g4, gF);
@@ -299,10 +403,7 @@ hipError_t launch_filter_T(const KParams &k, const float *gFbar, float *g4bar, f
     if (k.n_filt > 0) {
         hipLaunchKernelGGL(k_br_cos_T, dim3((unsigned)k.n_filt, cb), dim3(kElemThreads), 0, s, k,
                            gFbar, g4bar);
-        const int n_pairs = (k.n_psi + 1) / 2;
-        const size_t lds = (size_t)3 * k.fft_len * sizeof(float2);
-        hipLaunchKernelGGL(k_hilbert_T, dim3((unsigned)(k.n_filt * n_pairs)), dim3(kFftThreads), lds,
-                           s, k, g4bar);
+        launch_hilbert<true>(k, nullptr, g4bar, s);
         hipLaunchKernelGGL(k_fr_lw_T, dim3((unsigned)k.n_filt, cb), dim3(kElemThreads), 0, s, k,
                            g4bar, g2bar);
     }

@@ -36,6 +36,7 @@ struct KParams {
     const PiEntry *pi;
     const BpBox *boxes;
     int bp_tiles_x, bp_tiles_y, bp_runs, bp_kz;
+    int bp_all_fit;                    // every footprint box fits the LDS tile
     int gf_rows, gf_cols;              // padded g^F view (zero border kPad)
     int atan_deg;                      // < 0: atan2f
     float atan_coef[9];                // alpha/dalpha = t * sum_k atan_coef[k] t^(2k)

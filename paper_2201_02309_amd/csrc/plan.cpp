@@ -463,7 +463,7 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     // length-N DFT of the wrapped taps is i * Im with Im[f] = -2 sum_{m odd} K[m] sin(2 pi f m/N).
     P.fft_len = 1;
     while (P.fft_len < 2 * cols - 1) P.fft_len *= 2;
-    P.fft_len = std::max(P.fft_len, 16);
+    P.fft_len = std::max(P.fft_len, 64);          // smallest register-FFT shape
     const int N = P.fft_len;
     P.hil_im.assign(N, 0.0);
     for (int f = 0; f < N; ++f) {
@@ -625,6 +625,18 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
                 }
             }
         });
+    }
+
+    {
+        const BpBox *bx = reinterpret_cast<const BpBox *>(img + L.boxes);
+        const size_t nb = (size_t)P.bp_runs * P.bp_tiles_y * P.bp_tiles_x * P.W;
+        int mr = 0, mc = 0;
+        for (size_t i = 0; i < nb; ++i) {
+            mr = std::max(mr, (int)bx[i].nr);
+            mc = std::max(mc, (int)bx[i].nc);
+        }
+        P.bp_box_rows = mr;
+        P.bp_box_cols = mc;
     }
 
     // ------------------------------------------------------------------ workspace sizes

@@ -33,6 +33,10 @@ constexpr int kBpKZ = 16;
 // Rows / columns of zero padding around every filtered view g^F (so that clamped
 // bilinear taps outside the detector read exact zeros).
 constexpr int kPad = 2;
+// Largest footprint box the backprojector stages in LDS (rows x columns); a plan whose
+// boxes all fit lets the kernel drop its HBM fallback path.
+constexpr int kBpBoxRows = 32;
+constexpr int kBpBoxCols = 64;
 
 // Detector footprint (absolute row/col origin, may be -kPad, and extent) of one
 // backprojection tile x slice run at one pitch-relative view: every bilinear tap of
@@ -84,6 +88,7 @@ struct PlanHost {
     std::vector<uint8_t> fov;
     int32_t n_lo = 0, n_hi = 0, W = 0;
     int bp_tiles_x = 0, bp_tiles_y = 0, bp_runs = 0, bp_kz = kBpKZ;
+    int bp_box_rows = 0, bp_box_cols = 0;  // largest footprint box
     int64_t first_view = 0, last_view = -1, n_vv = 0, n_valid = 0;
 
     // Hilbert
