@@ -105,6 +105,10 @@ typedef struct katsevich_plan_info {
     int32_t gf_rows, gf_cols;          /* padded g^F view of katsevich_filter (see below) */
     int32_t atan_degree;               /* degree in t^2 of the backprojector's atan polynomial
                                           (-1: library atan2f) */
+    int32_t bp_slices;                 /* slices per backprojection register run */
+    int32_t bp_box_rows, bp_box_cols;  /* largest detector footprint box of a backprojection
+                                          tile; boxes up to 32 x 64 are staged in LDS, a plan
+                                          with larger ones uses the kernel with an HBM path */
     int32_t reserved;
 } katsevich_plan_info;
 
@@ -167,22 +171,17 @@ int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF,
  * first pitch's tables): d_gF as written by katsevich_filter -> d_vol.  Asynchronous. */
 int katsevich_backproject(katsevich_plan_t plan, const float *d_gF, float *d_vol, void *stream);
 
-/* Size in bytes of the device queue buffer katsevich_backproject_batch needs for n plans
- * (task descriptors and the work counter); 0 for n < 1. */
-uint64_t katsevich_batch_queue_bytes(int n_plans);
-
-/* Packed backprojection of n reconstructions in one persistent launch (serving): item i
- * backprojects d_gF[i] (katsevich_filter output of plans[i]) into d_vol[i], exactly as
- * katsevich_backproject would (bit-identical results).  Workgroups take (plan, pitch,
- * slice run, tile) tasks from a device counter, so reconstructions of different sizes,
- * pitches and grids share the GPU in one launch.  All plans must be bound and use the same
- * bp_slices.  d_queue: caller device buffer of katsevich_batch_queue_bytes(n) bytes
- * (256-byte aligned), overwritten; it must not be reused by another launch before this one
- * has finished.  Asynchronous on stream.  Errors: KATS_EINVAL, KATS_ENOTBOUND,
- * KATS_EWORKSPACE, KATS_EHIP. */
+/* Grouped backprojection of n reconstructions (serving): item i backprojects d_gF[i]
+ * (katsevich_filter output of plans[i]) into d_vol[i], exactly as katsevich_backproject
+ * would (bit-identical results).  One launch covers the (pitch, slice run, tile) tasks of
+ * up to 16 items, so reconstructions of different sizes, pitches and grids fill the GPU
+ * together; items whose footprint boxes all fit the kernel's LDS tile are grouped apart
+ * from the others (see bp_box_rows / bp_box_cols of katsevich_plan_info).  All plans
+ * must be bound and use the same bp_slices.  No device memory besides the arrays named;
+ * the host arrays may be reused when the call returns.  Asynchronous on stream.
+ * Errors: KATS_EINVAL, KATS_ENOTBOUND, KATS_EHIP. */
 int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *const *d_gF,
-                                float *const *d_vol, int n, void *d_queue, uint64_t queue_bytes,
-                                void *stream);
+                                float *const *d_vol, int n, void *stream);
 
 /* Exact adjoint of katsevich_recon (transpose of the discrete operator): d_grad_vol
  * float32 [nz][ny][nx] -> d_grad_sino float32 [n_views][rows][cols] (overwritten).

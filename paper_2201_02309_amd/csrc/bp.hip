@@ -33,6 +33,24 @@ __device__ inline int wave_max(int v) {
 
 __device__ inline float med3(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 
+// Pointers read from memory (the packed launch's request descriptors) carry no address
+// space, so loads through them would be flat (slower, and ordered with LDS traffic);
+// every table / g^F / volume access goes through a global-address-space pointer instead.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T *glb(T *ptr) {
+    return (__attribute__((address_space(1))) T *)ptr;
+}
+// Load of a 4-, 8- or 16-byte value through a global-address-space pointer.
+template <class T>
+__device__ inline T ldg(const T *ptr) {
+    static_assert(sizeof(T) % 4 == 0 && sizeof(T) <= 16, "whole dwords");
+    typedef unsigned int W __attribute__((ext_vector_type(sizeof(T) / 4)));
+    const W w = *(const __attribute__((address_space(1))) W *)ptr;
+    T out;
+    __builtin_memcpy(&out, &w, sizeof(T));
+    return out;
+}
+
 // ---------------------------------------------------------------------------------
 // Forward backprojection.  Workgroup = 256 lanes = a 16 x 16 (x, y) tile (4 waves of
 // 16 x 4) x a run of KZ consecutive slices of one pitch; every lane keeps KZ accumulators.
@@ -69,7 +87,8 @@ struct BpArgs {
     float atan_coef[9];
 };
 
-__device__ inline float lerp_bilinear(const float *t, int pitch_f, float tc, float tr) {
+template <class P>
+__device__ inline float lerp_bilinear(P t, int pitch_f, float tc, float tr) {
     const float v00 = t[0], v01 = t[1], v10 = t[pitch_f], v11 = t[pitch_f + 1];
     const float top = fmaf(tc, v01 - v00, v00);
     const float bot = fmaf(tc, v11 - v10, v10);
@@ -125,7 +144,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
             B[jj] = -3.0e38f;
             acc[jj] = 0.0f;
             if (inxy && jj < nrun) {
-                const PiEntry e = p.pi[((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix];
+                const PiEntry e = ldg(p.pi + ((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix);
                 const long long nf = base + e.nf, nl = base + e.nl;
                 if (e.nf <= e.nl && nf - 1 >= 0 && nl + 1 <= p.n_views - 1) {
                     A[jj] = e.li - 0.5f;      // c_n = clamp(min(m - A, B - m), 0, 1)
@@ -197,24 +216,25 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
     const int srow = tid >> 4, scol = (tid & 15) * 4;
     uint2 bw_next = make_uint2(0u, 0u);   // box of the view after the current one
     if (mlo <= mhi) {
-        const BpBox b = unpack(boxes[mlo]);
-        if (mlo < mhi) bw_next = boxes[mlo + 1];
+        const BpBox b = unpack(ldg(boxes + mlo));
+        if (mlo < mhi) bw_next = ldg(boxes + mlo + 1);
         if (fits(b)) {
             const float *src = gF0 + (size_t)mlo * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad);
             if (srow < b.nr && scol < b.nc)
                 *reinterpret_cast<float4 *>(&lds[0][srow * kLP + scol]) =
-                    *reinterpret_cast<const float4 *>(src + srow * cpitch + scol);
+                    ldg(reinterpret_cast<const float4 *>(src + srow * cpitch + scol));
             if (srow + 16 < b.nr && scol < b.nc)
                 *reinterpret_cast<float4 *>(&lds[0][(srow + 16) * kLP + scol]) =
-                    *reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol);
+                    ldg(reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol));
         }
     }
     __syncthreads();
-    BpBox b = unpack(boxes[mlo <= mhi ? mlo : 0]);
+    BpBox b = unpack(ldg(boxes + (mlo <= mhi ? mlo : 0)));
     for (int m = mlo; m <= mhi; ++m) {
         const int buf = (m - mlo) & 1;
         // box of view m+2, loaded one iteration ahead of its use
-        const uint2 bw_after = (m + 2 <= mhi) ? boxes[m + 2] : make_uint2(0u, 0u);
+        uint2 bw_after = make_uint2(0u, 0u);
+        if (m + 2 <= mhi) bw_after = ldg(boxes + m + 2);
         // prefetch the next view's box into registers (two rows of 16 float4 lanes)
         float4 pf0, pf1;
         BpBox bn = b;
@@ -226,13 +246,13 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
                 const float *src = gF0 + (size_t)(m + 1) * vstride + (bn.r0 + kPad) * cpitch + (bn.c0 + kPad);
                 st0 = srow < bn.nr && scol < bn.nc;
                 st1 = srow + 16 < bn.nr && scol < bn.nc;
-                if (st0) pf0 = *reinterpret_cast<const float4 *>(src + srow * cpitch + scol);
-                if (st1) pf1 = *reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol);
+                if (st0) pf0 = ldg(reinterpret_cast<const float4 *>(src + srow * cpitch + scol));
+                if (st1) pf1 = ldg(reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol));
             }
         }
         // per (lane, view) geometry; coordinates relative to the box origin, clamped into
         // the box (only voxels projecting outside the zero-padded detector are clamped)
-        const float4 vt = view_tab[m];
+        const float4 vt = ldg(view_tab + m);
         const float u = fmaf(-x, vt.y, y * vt.x);
         const float v = p.R - fmaf(x, vt.x, y * vt.y);
         const float vinv = __builtin_amdgcn_rcpf(v);
@@ -267,7 +287,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
         if (use_words) word = __builtin_amdgcn_readfirstlane(words[wave][m - mlo]);
         // one group of kKG slices: taps of all its slices first (independent LDS / HBM
         // loads), then the accumulation with or without the coverage weight
-        auto group = [&](const float *T, int tp, int g) {
+        auto group = [&](auto T, int tp, int g) {         // T: LDS or global taps
             float val[kKG];
 #pragma unroll
             for (int s = 0; s < kKG; ++s) {
@@ -293,7 +313,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
             for (int g = 0; g < NG; ++g)
                 if (word & (1u << g)) group(T, kLP, g);
         } else {
-            const float *T = gF0 + (size_t)m * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad) + c0;
+            const auto T = glb(gF0 + (size_t)m * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad) + c0);
 #pragma unroll
             for (int g = 0; g < NG; ++g)
                 if (word & (1u << g)) group(T, cpitch, g);
@@ -312,7 +332,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
 #pragma unroll
     for (int jj = 0; jj < KZ; ++jj) {
         if (jj < nrun)
-            vol[((size_t)(iz0 + jj) * p.ny + iy) * p.nx + ix] =
+            glb(vol)[((size_t)(iz0 + jj) * p.ny + iy) * p.nx + ix] =
                 ((valid >> jj) & 1u) ? acc[jj] * p.scale : 0.0f;
     }
 }
@@ -327,10 +347,12 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
 }
 
 // ---------------------------------------------------------------------------------
-// Packed backprojection of several plans in one persistent launch: every workgroup takes
-// the next task index from a device counter (one atomic per task), finds the request
-// owning it from the task prefix, and runs that request's tile.  The loop ends for every
-// workgroup once the counter passes the task count (no workgroup waits on another).
+// Grouped backprojection of several plans in one launch (serving): the grid enumerates
+// the (pitch, slice run, tile) tasks of up to kGroupMax requests back to back; a block
+// finds its request from the task prefix held in the kernel argument (a wave-uniform scan)
+// and runs that request's tile exactly as the one-plan kernel does.  Descriptors travel as
+// kernel arguments, so the compiler sees them as constant memory (scalar loads, global
+// pointers), as for the one-plan kernel.
 // ---------------------------------------------------------------------------------
 struct BpRequest {
     BpArgs a;
@@ -339,45 +361,28 @@ struct BpRequest {
     const float4 *view;
     const uint2 *boxes;
     long long first_task;          // prefix of the task counts of earlier requests
-    long long n_tasks;
 };
 
-constexpr int kDescPerLaunch = 16;
-struct BpRequestChunk {
-    BpRequest r[kDescPerLaunch];
-    int n, offset;
+constexpr int kGroupMax = 16;
+struct BpGroup {
+    BpRequest r[kGroupMax];
+    int n;
 };
-
-// writes descriptors (kernel arguments are captured at launch) and clears the counter
-__global__ void k_write_requests(BpRequestChunk c, BpRequest *__restrict__ dst,
-                                 unsigned *__restrict__ counter) {
-    const int i = threadIdx.x;
-    if (i < c.n) dst[c.offset + i] = c.r[i];
-    if (c.offset == 0 && i == 0) *counter = 0u;
-}
+static_assert(sizeof(BpGroup) <= 4000, "kernel argument segment");
 
 template <int KZ, bool FB>
-__global__ __launch_bounds__(kNT) void k_bp_queue(const BpRequest *__restrict__ reqs, int n_req,
-                                                  long long n_tasks, unsigned *__restrict__ counter) {
+__global__ __launch_bounds__(kNT) void k_bp_group(const BpGroup g) {
     __shared__ BpShared S;
-    __shared__ unsigned task_sh;
-    for (;;) {
-        if (threadIdx.x == 0) task_sh = atomicAdd(counter, 1u);
-        __syncthreads();
-        const long long task = (long long)__builtin_amdgcn_readfirstlane((int)task_sh);
-        __syncthreads();
-        if (task >= n_tasks) break;
-        int r = 0;
-        while (r + 1 < n_req && reqs[r + 1].first_task <= task) ++r;
-        const BpRequest &q = reqs[r];
-        long long local = task - q.first_task;
-        const int bxi = (int)(local % q.a.tiles_x);
-        local /= q.a.tiles_x;
-        const int byi = (int)(local % q.a.tiles_y);
-        const int bz = (int)(local / q.a.tiles_y);
-        bp_tile<KZ, FB>(q.a, q.gF, q.vol, q.view, q.boxes, bxi, byi, bz, S);
-        __syncthreads();
-    }
+    const long long task = blockIdx.x;
+    int r = 0;
+    while (r + 1 < g.n && g.r[r + 1].first_task <= task) ++r;
+    const BpRequest &q = g.r[r];
+    long long local = task - q.first_task;
+    const int bxi = (int)(local % q.a.tiles_x);
+    local /= q.a.tiles_x;
+    const int byi = (int)(local % q.a.tiles_y);
+    const int bz = (int)(local / q.a.tiles_y);
+    bp_tile<KZ, FB>(q.a, q.gF, q.vol, q.view, q.boxes, bxi, byi, bz, S);
 }
 
 // ---------------------------------------------------------------------------------
@@ -521,46 +526,44 @@ hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hip
     return hipGetLastError();
 }
 
-uint64_t batch_queue_bytes(int n) {
-    return ((uint64_t)n * sizeof(BpRequest) + 255) / 256 * 256 + 256;
-}
-
+// Requests whose boxes all fit the LDS tile run in launches without the HBM path, the
+// others in launches with it; each launch takes up to kGroupMax requests.
 hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, float *const *vol,
-                                    int n, void *queue, int kz, int grid_limit, hipStream_t s) {
-    BpRequest *reqs = static_cast<BpRequest *>(queue);
-    unsigned *counter = reinterpret_cast<unsigned *>(static_cast<unsigned char *>(queue) +
-                                                     batch_queue_bytes(n) - 256);
-    long long total = 0;
-    bool fb = false;
-    for (int i = 0; i < n; ++i) fb = fb || !ks[i].bp_all_fit;
-    for (int base = 0; base < n; base += kDescPerLaunch) {
-        BpRequestChunk c{};
-        c.offset = base;
-        c.n = n - base < kDescPerLaunch ? n - base : kDescPerLaunch;
-        for (int i = 0; i < c.n; ++i) {
-            const KParams &k = ks[base + i];
-            BpRequest &q = c.r[i];
+                                    int n, int kz, hipStream_t s) {
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool fb = pass == 1;
+        BpGroup grp{};
+        long long total = 0;
+        auto flush = [&]() {
+            if (grp.n == 0) return;
+            const dim3 grid((unsigned)total);
+#define KATS_BPG_LAUNCH(KZ, FB) hipLaunchKernelGGL((k_bp_group<KZ, FB>), grid, dim3(kNT), 0, s, grp)
+            switch (kz) {
+                case 8: if (fb) KATS_BPG_LAUNCH(8, true); else KATS_BPG_LAUNCH(8, false); break;
+                case 32: if (fb) KATS_BPG_LAUNCH(32, true); else KATS_BPG_LAUNCH(32, false); break;
+                default: if (fb) KATS_BPG_LAUNCH(16, true); else KATS_BPG_LAUNCH(16, false); break;
+            }
+#undef KATS_BPG_LAUNCH
+            grp = BpGroup{};
+            total = 0;
+        };
+        for (int i = 0; i < n; ++i) {
+            const KParams &k = ks[i];
+            if ((k.bp_all_fit == 0) != fb) continue;
+            const long long tasks = (long long)k.bp_tiles_x * k.bp_tiles_y * k.n_pitches * k.bp_runs;
+            if (tasks == 0) continue;
+            if (grp.n == kGroupMax || total + tasks > 0x7fffffffLL) flush();
+            BpRequest &q = grp.r[grp.n++];
             q.a = bp_args(k);
-            q.gF = gF[base + i];
-            q.vol = vol[base + i];
+            q.gF = gF[i];
+            q.vol = vol[i];
             q.view = k.view;
             q.boxes = reinterpret_cast<const uint2 *>(k.boxes);
-            q.n_tasks = (long long)k.bp_tiles_x * k.bp_tiles_y * k.n_pitches * k.bp_runs;
             q.first_task = total;
-            total += q.n_tasks;
+            total += tasks;
         }
-        hipLaunchKernelGGL(k_write_requests, dim3(1), dim3(64), 0, s, c, reqs, counter);
+        flush();
     }
-    if (total == 0) return hipGetLastError();
-    const long long g = total < grid_limit ? total : grid_limit;
-#define KATS_BPQ_LAUNCH(KZ, FB) \
-    hipLaunchKernelGGL((k_bp_queue<KZ, FB>), dim3((unsigned)g), dim3(kNT), 0, s, reqs, n, total, counter)
-    switch (kz) {
-        case 8: if (fb) KATS_BPQ_LAUNCH(8, true); else KATS_BPQ_LAUNCH(8, false); break;
-        case 32: if (fb) KATS_BPQ_LAUNCH(32, true); else KATS_BPQ_LAUNCH(32, false); break;
-        default: if (fb) KATS_BPQ_LAUNCH(16, true); else KATS_BPQ_LAUNCH(16, false); break;
-    }
-#undef KATS_BPQ_LAUNCH
     return hipGetLastError();
 }
 

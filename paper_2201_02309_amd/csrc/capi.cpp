@@ -173,6 +173,9 @@ int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
     i.gf_rows = P.gf_rows;
     i.gf_cols = P.gf_cols;
     i.atan_degree = P.atan_deg;
+    i.bp_slices = P.bp_kz;
+    i.bp_box_rows = P.bp_box_rows;
+    i.bp_box_cols = P.bp_box_cols;
     *out = i;
     return KATS_OK;
 }
@@ -305,19 +308,11 @@ int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, flo
     return KATS_OK;
 }
 
-uint64_t katsevich_batch_queue_bytes(int n_plans) {
-    return n_plans > 0 ? kats::batch_queue_bytes(n_plans) : 0;
-}
-
 int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *const *d_gF,
-                                float *const *d_vol, int n, void *d_queue, uint64_t queue_bytes,
-                                void *stream) {
+                                float *const *d_vol, int n, void *stream) {
     g_err.clear();
-    if (!plans || !d_gF || !d_vol || !d_queue || n < 1)
+    if (!plans || !d_gF || !d_vol || n < 1)
         return fail(KATS_EINVAL, "katsevich_backproject_batch: null argument or n < 1");
-    if (queue_bytes < kats::batch_queue_bytes(n))
-        return fail(KATS_EWORKSPACE, "katsevich_backproject_batch: queue buffer too small");
-    if (!aligned256(d_queue)) return fail(KATS_EINVAL, "katsevich_backproject_batch: queue not 256-byte aligned");
     std::vector<kats::KParams> ks((size_t)n);
     int kz = -1;
     for (int i = 0; i < n; ++i) {
@@ -330,11 +325,7 @@ int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *cons
             return fail(KATS_EINVAL, "katsevich_backproject_batch: plans use different bp_slices");
         ks[(size_t)i] = kats::make_params(plans[i]->P);
     }
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 256;
-    hipError_t e = kats::launch_backproject_batch(ks.data(), d_gF, d_vol, n, d_queue, kz, 4 * cus,
+    hipError_t e = kats::launch_backproject_batch(ks.data(), d_gF, d_vol, n, kz,
                                                   static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "katsevich_backproject_batch: launch");
     return KATS_OK;

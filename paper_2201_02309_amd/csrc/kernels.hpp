@@ -51,11 +51,10 @@ hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *
 // Backprojection of every pitch (reusing the first pitch's tables).
 hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s);
 
-// Packed backprojection of n bound plans in one persistent work-queue launch.  queue:
-// device buffer of batch_queue_bytes(n) bytes; kz: the plans' common slice run.
-uint64_t batch_queue_bytes(int n);
+// Grouped backprojection of n bound plans (one launch per group of up to 16 plans, the
+// plans whose boxes fit the LDS tile grouped apart); kz: the plans' common slice run.
 hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, float *const *vol,
-                                    int n, void *queue, int kz, int grid_limit, hipStream_t s);
+                                    int n, int kz, hipStream_t s);
 
 // Adjoint pieces.
 hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFbar, hipStream_t s);

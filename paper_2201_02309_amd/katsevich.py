@@ -50,7 +50,8 @@ class _Info(ctypes.Structure):
                 ("slices_per_pitch", c_int32), ("n_table_slices", c_int32), ("n_psi", c_int32),
                 ("window_views", c_int32), ("window_lo", c_int32), ("fft_len", c_int32),
                 ("commensurate", c_int32), ("gf_rows", c_int32), ("gf_cols", c_int32),
-                ("atan_degree", c_int32), ("reserved", c_int32)]
+                ("atan_degree", c_int32), ("bp_slices", c_int32), ("bp_box_rows", c_int32),
+                ("bp_box_cols", c_int32), ("reserved", c_int32)]
 
 
 # table id -> (C enum, numpy dtype, shape key)
@@ -65,8 +66,7 @@ TABLES = {
 EXPORTED = ["katsevich_plan", "katsevich_plan_query", "katsevich_plan_bind",
             "katsevich_plan_export", "katsevich_recon", "katsevich_filter",
             "katsevich_backproject", "katsevich_recon_backward", "katsevich_backproject_batch",
-            "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error",
-            "katsevich_batch_queue_bytes"]
+            "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error"]
 
 _lib = None
 
@@ -91,10 +91,7 @@ def load_library(path: str = LIB_PATH):
     lib.katsevich_recon_backward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_uint64,
                                              c_void_p]
     lib.katsevich_backproject_batch.argtypes = [POINTER(c_void_p), POINTER(c_void_p),
-                                                POINTER(c_void_p), c_int, c_void_p, c_uint64,
-                                                c_void_p]
-    lib.katsevich_batch_queue_bytes.argtypes = [c_int]
-    lib.katsevich_batch_queue_bytes.restype = c_uint64
+                                                POINTER(c_void_p), c_int, c_void_p]
     lib.katsevich_plan_destroy.argtypes = [c_void_p]
     lib.katsevich_plan_destroy.restype = None
     lib.katsevich_status_string.argtypes = [c_int]
@@ -291,9 +288,9 @@ def backproject(plan: Plan, gF, out=None):
     return out
 
 
-def backproject_batch(plans, gFs, vols=None, queue=None):
-    """katsevich_backproject_batch: one persistent launch backprojecting every
-    (plans[i], gFs[i]) into vols[i] (allocated if None).  Returns the volumes."""
+def backproject_batch(plans, gFs, vols=None):
+    """katsevich_backproject_batch: grouped launches backprojecting every (plans[i], gFs[i])
+    into vols[i] (allocated if None).  Returns the volumes."""
     import torch
     n = len(plans)
     if n == 0:
@@ -305,16 +302,11 @@ def backproject_batch(plans, gFs, vols=None, queue=None):
     for p, g, v in zip(plans, gFs, vols):
         _require(g, filtered_shape(p), "gF")
         _require(v, _vol_shape(p), "vol")
-    need = int(lib.katsevich_batch_queue_bytes(n))
-    if queue is None or queue.numel() < need:
-        queue = torch.empty(need, dtype=torch.uint8, device=gFs[0].device)
     arr = c_void_p * n
     hp = arr(*[p.handle.value for p in plans])
     hg = arr(*[g.data_ptr() for g in gFs])
     hv = arr(*[v.data_ptr() for v in vols])
-    _check(lib, lib.katsevich_backproject_batch(hp, hg, hv, n, c_void_p(queue.data_ptr()),
-                                                c_uint64(queue.numel()),
-                                                _stream_handle(gFs[0].device)))
+    _check(lib, lib.katsevich_backproject_batch(hp, hg, hv, n, _stream_handle(gFs[0].device)))
     return vols
 
 

@@ -8,10 +8,12 @@ The server
 * admits ready requests first-come-first-served while their device footprint (sinogram
   copy, filter workspace, g^F, volume) fits the HBM budget, otherwise they wait until
   earlier requests finish and free memory,
-* launches every admitted group as the per-request filter kernels followed by ONE packed
-  backprojection (``katsevich_backproject_batch``: a persistent launch whose workgroups
-  take tiles of all requests from a shared work queue), alternating between two streams so
-  a new group's filtering overlaps the previous group's backprojection,
+* launches every admitted group as the per-request filter kernels followed by one grouped
+  backprojection (``katsevich_backproject_batch``: the tiles of all the group's requests in
+  one grid, so small reconstructions fill the GPU together), alternating between two streams
+  so that a new group's filtering overlaps the previous group's backprojection; a group is
+  closed once its backprojection work (voxel-view updates) reaches ``group_work``, which
+  bounds the latency a request waits for its group-mates,
 * records per-request latency (completion event time - arrival) and throughput.
 
 Every reconstruction step runs in libkatsevich; this module only schedules.  The packed
@@ -158,15 +160,15 @@ class Admission:
 
 class Server:
     def __init__(self, plan_cache: PlanCache, budget_bytes: float = 200e9, max_batch: int = 32,
-                 keep_volumes: bool = False, n_streams: int = 2):
+                 keep_volumes: bool = False, n_streams: int = 2, group_work: float = 2.0e10):
         import torch
         self.cache = plan_cache
         self.device = plan_cache.device
         self.admission = Admission(int(budget_bytes))
         self.max_batch = max_batch
+        self.group_work = float(group_work)
         self.keep_volumes = keep_volumes
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
-        self.queues = [None] * n_streams
 
     def _launch(self, si, batch):
         import torch
@@ -184,12 +186,7 @@ class Server:
                 gFs.append(gF)
                 vols.append(vol)
                 held.append((sino, ws, gF))
-            need = int(plans[0]._lib.katsevich_batch_queue_bytes(len(plans)))
-            q = self.queues[si]
-            if q is None or q.numel() < need:
-                q = self.queues[si] = torch.empty(max(need, 4096), dtype=torch.uint8,
-                                                  device=self.device)
-            K.backproject_batch(plans, gFs, vols, queue=q)
+            K.backproject_batch(plans, gFs, vols)
             ev = torch.cuda.Event()
             ev.record(s)
         return ev, vols, held
@@ -226,6 +223,7 @@ class Server:
             if free and waiting:
                 batch, rest = [], []
                 blocked = False
+                work = 0.0
                 for r, key in waiting:
                     plan = self.cache.poll(key)
                     if plan is None:
@@ -236,9 +234,11 @@ class Server:
                         r.plan_seconds = self.cache.build_seconds.get(key, 0.0)
                         r.footprint = footprint(plan)
                     if not blocked and len(batch) < self.max_batch and \
+                            (not batch or work < self.group_work) and \
                             self.admission.try_admit(r.footprint):
                         r.t_admit = time.perf_counter() - t0
                         batch.append((r, plan))
+                        work += float(plan.info["n_vv"])
                     else:
                         blocked = True                       # keep arrival order
                         rest.append((r, key))

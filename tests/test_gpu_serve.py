@@ -1,4 +1,4 @@
-"""GPU tests of the packed multi-request backprojection and the serving loop: every
+"""GPU tests of the grouped multi-request backprojection and the serving loop: every
 request's volume is bit-identical alone (plain katsevich_recon) and in the mix."""
 import numpy as np
 import pytest
@@ -37,10 +37,23 @@ def _small_requests():
     return out
 
 
+def _wide_box_request():
+    """A scan whose backprojection footprint boxes exceed the LDS tile (wide fan of fine
+    columns over coarse voxels), so its tiles take the kernel path with HBM taps."""
+    wl = configs.tiny(nxy=24, nz=12, cols=160, rows=8, views_per_turn=72, turns=3, feed=24.0,
+                      dxy=8.0, seed=61)
+    g, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    return g, gr, phantom.project(ph, g).astype(np.float32)
+
+
 def test_packed_backprojection_equals_single_launches():
     dev = _dev()
-    reqs = _small_requests()
+    # 19 items: more than one group of 16, both kernel paths
+    reqs = (_small_requests() * 4)[:18] + [_wide_box_request()]
     plans = [K.Plan(g, gr, device=0) for g, gr, _ in reqs]
+    fits = [p.info["bp_box_rows"] <= 32 and p.info["bp_box_cols"] <= 64 for p in plans]
+    assert any(fits) and not all(fits)
     gFs = [K.filter_views(p, torch.from_numpy(s).to(dev)) for p, (_, _, s) in zip(plans, reqs)]
     alone = [K.backproject(p, gF) for p, gF in zip(plans, gFs)]
     mixed = K.backproject_batch(plans, gFs)
