@@ -112,6 +112,7 @@ def serving_bench(n_requests=24, rate=20.0, budget=200e9):
           flush=True)
     out = {"workload": f"serving recipe, {n_requests} requests, Poisson {rate:g}/s and saturated",
            "hbm_budget_bytes": budget, "warm_plans": True,
+           "group_work_updates": serve.GROUP_WORK,
            "plan_build_s_mean": float(np.mean(builds)), "plan_build_s_max": float(np.max(builds)),
            "n_vv_total": int(sum(cache.plans[k].info["n_vv"] for k in keys))}
     for name, saturated in (("poisson", False), ("saturated", True)):
@@ -119,12 +120,15 @@ def serving_bench(n_requests=24, rate=20.0, budget=200e9):
         mk = lambda: [serve.Request(rid=i, arrival=float(t), geom=wl.geom.as_dict(),
                                     grid=wl.grid.as_dict(), sino=sinos[i])
                       for i, (wl, t) in enumerate(zip(wls, arr))]
-        # warm the allocator / kernels once, untimed
-        serve.Server(cache, budget_bytes=budget).run(mk()[:4])
-        torch.cuda.synchronize()
+        # one server (one HBM arena of the budget) warmed on four requests, untimed
         srv = serve.Server(cache, budget_bytes=budget)
+        srv.run(mk()[:4])
+        torch.cuda.synchronize()
         served = serve.summarize(srv.run(mk()))
         torch.cuda.synchronize()
+        srv.close()
+        del srv
+        torch.cuda.empty_cache()
         seq = serve.summarize(serve.serve_sequential(cache, mk()))
         out[f"served_{name}"] = served
         out[f"sequential_{name}"] = seq

@@ -6,8 +6,9 @@ The server
 * builds the float64 plan of each new geometry on host worker threads (plans are cached by
   the exact geometry/grid tuple and bound to device tables once),
 * admits ready requests first-come-first-served while their device footprint (sinogram
-  copy, filter workspace, g^F, volume) fits the HBM budget, otherwise they wait until
-  earlier requests finish and free memory,
+  copy, filter workspace, g^F, volume) gets a contiguous block of the server's HBM arena
+  (one buffer of the budget's size, first-fit), otherwise they wait until earlier requests
+  finish and free their blocks,
 * launches every admitted group as the per-request filter kernels followed by one grouped
   backprojection (``katsevich_backproject_batch``: the tiles of all the group's requests in
   one grid, so small reconstructions fill the GPU together), alternating between two streams
@@ -52,6 +53,7 @@ class Request:
     cache_hit: bool = False
     plan_seconds: float = 0.0
     footprint: int = 0
+    offset: int = 0              # arena byte offset while in flight
     volume: object = None
 
     @property
@@ -129,73 +131,141 @@ class PlanCache:
         self._pool.shutdown(wait=True)
 
 
+_ALIGN = 256
+
+
+def _up(n: int) -> int:
+    return (int(n) + _ALIGN - 1) // _ALIGN * _ALIGN
+
+
+def layout(plan: K.Plan):
+    """Byte offsets of a request's device buffers inside its arena block: sinogram copy,
+    filter workspace, g^F, volume (each 256-byte aligned); returns (offsets, total)."""
+    g, gr = plan.geom, plan.grid
+    sizes = (int(g["n_views"]) * int(g["det_rows"]) * int(g["det_cols"]) * 4,
+             max(int(plan.info["workspace_bytes_filter"]), _ALIGN),
+             int(plan.info["filtered_bytes"]),
+             int(gr["nx"]) * int(gr["ny"]) * int(gr["nz"]) * 4)
+    offs, o = [], 0
+    for n in sizes:
+        offs.append(o)
+        o += _up(n)
+    return offs, o
+
+
 def footprint(plan: K.Plan) -> int:
     """Device bytes a request holds while in flight."""
-    g = plan.geom
-    sino = int(g["n_views"]) * int(g["det_rows"]) * int(g["det_cols"]) * 4
-    gr = plan.grid
-    vol = int(gr["nx"]) * int(gr["ny"]) * int(gr["nz"]) * 4
-    return sino + int(plan.info["workspace_bytes_filter"]) + int(plan.info["filtered_bytes"]) + vol
+    return layout(plan)[1]
 
 
-class Admission:
-    """First-come-first-served admission under a byte budget (pure policy)."""
+class Arena:
+    """First-fit allocation of 256-byte-aligned ranges of one device buffer (host-side
+    bookkeeping; the admission test of the server).  A request is admitted when its whole
+    footprint gets one contiguous range, so admitted work never waits on the framework's
+    allocator and the budget is exact."""
 
-    def __init__(self, budget_bytes: int):
-        self.budget = int(budget_bytes)
+    def __init__(self, nbytes: int):
+        self.size = int(nbytes) // _ALIGN * _ALIGN
+        self.free = [(0, self.size)] if self.size else []     # sorted, coalesced
         self.used = 0
 
-    def try_admit(self, nbytes: int) -> bool:
-        if nbytes > self.budget:
-            raise ValueError(f"request footprint {nbytes} B exceeds the whole budget {self.budget} B")
-        if self.used + nbytes <= self.budget:
-            self.used += nbytes
-            return True
-        return False
+    def alloc(self, nbytes: int):
+        n = _up(nbytes)
+        if n > self.size:
+            raise ValueError(f"request footprint {n} B exceeds the whole budget {self.size} B")
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (o + n, sz - n)
+                self.used += n
+                return o
+        return None
 
-    def release(self, nbytes: int):
-        self.used -= nbytes
+    def release(self, offset: int, nbytes: int):
+        n = _up(nbytes)
+        self.used -= n
         assert self.used >= 0
+        i = 0
+        while i < len(self.free) and self.free[i][0] < offset:
+            i += 1
+        self.free.insert(i, (offset, n))
+        # coalesce with the right, then the left neighbour
+        if i + 1 < len(self.free) and self.free[i][0] + self.free[i][1] == self.free[i + 1][0]:
+            self.free[i] = (self.free[i][0], self.free[i][1] + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+
+# Backprojection work (voxel-view updates) after which a group is closed: ~2 ms of the
+# backprojector, short enough that a request rarely waits long for its group-mates and
+# long enough that small reconstructions share launches.
+GROUP_WORK = 3.0e9
 
 
 class Server:
+    """Continuous-batching server.  All request buffers live in one device arena of
+    budget_bytes (allocated on the first run, kept across runs, freed by close())."""
+
     def __init__(self, plan_cache: PlanCache, budget_bytes: float = 200e9, max_batch: int = 32,
-                 keep_volumes: bool = False, n_streams: int = 2, group_work: float = 2.0e10):
+                 keep_volumes: bool = False, n_streams: int = 2, group_work: float = GROUP_WORK):
         import torch
         self.cache = plan_cache
         self.device = plan_cache.device
-        self.admission = Admission(int(budget_bytes))
+        self.arena = Arena(int(budget_bytes))
+        self._buf = None
         self.max_batch = max_batch
         self.group_work = float(group_work)
         self.keep_volumes = keep_volumes
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
 
+    def close(self):
+        self._buf = None
+
+    def _views(self, r, plan):
+        """Tensors of request r inside its arena block."""
+        import torch
+        offs, _ = layout(plan)
+        g, gr = plan.geom, plan.grid
+        base = r.offset
+
+        def view(i, shape, dtype):
+            n = int(np.prod(shape)) * (4 if dtype == torch.float32 else 1)
+            return self._buf[base + offs[i]: base + offs[i] + n].view(dtype).view(shape)
+        sino = view(0, (int(g["n_views"]), int(g["det_rows"]), int(g["det_cols"])), torch.float32)
+        ws = view(1, (max(int(plan.info["workspace_bytes_filter"]), _ALIGN),), torch.uint8)
+        gF = view(2, K.filtered_shape(plan), torch.float32)
+        vol = view(3, K._vol_shape(plan), torch.float32)
+        return sino, ws, gF, vol
+
     def _launch(self, si, batch):
         import torch
         s = self.streams[si]
-        plans, gFs, vols, held = [], [], [], []
+        plans, gFs, vols = [], [], []
         with torch.cuda.stream(s):
             for r, plan in batch:
-                sino = r.sino.clone()                      # D2D copy into the request's slot
-                ws = torch.empty(max(int(plan.info["workspace_bytes_filter"]), 256),
-                                 dtype=torch.uint8, device=self.device)
-                gF = K.filter_views(plan, sino, ws=ws)
-                vol = torch.empty(K._vol_shape(plan), dtype=torch.float32,
-                                  device=self.device)
+                sino, ws, gF, vol = self._views(r, plan)
+                sino.copy_(r.sino)                         # D2D copy into the request's slot
+                K.filter_views(plan, sino, out=gF, ws=ws)
                 plans.append(plan)
                 gFs.append(gF)
                 vols.append(vol)
-                held.append((sino, ws, gF))
             K.backproject_batch(plans, gFs, vols)
             ev = torch.cuda.Event()
             ev.record(s)
-        return ev, vols, held
+        return ev, vols
 
     def run(self, requests, clock_start=None):
         """Serve requests (sorted by arrival); returns them with timings filled in."""
+        import torch
+        if self._buf is None:
+            self._buf = torch.empty(self.arena.size, dtype=torch.uint8, device=self.device)
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         waiting = []                                   # arrived, plan maybe not ready
-        inflight = [None] * len(self.streams)          # (event, batch, vols, held)
+        inflight = [None] * len(self.streams)          # (event, batch, vols)
         t0 = time.perf_counter() if clock_start is None else clock_start
         done = []
         n = len(pending)
@@ -206,18 +276,20 @@ class Server:
                 key, hit = self.cache.request(r.geom, r.grid)
                 r.cache_hit = hit
                 waiting.append((r, key))
-            # completions
+            # completions: the group's stream has finished, its arena blocks are free again
             for si, item in enumerate(inflight):
                 if item is not None and item[0].query():
                     tdone = time.perf_counter() - t0
-                    _, batch, vols, held = item
+                    _, batch, vols = item
                     for (r, plan), v in zip(batch, vols):
                         r.t_done = tdone
-                        r.volume = v if self.keep_volumes else None
-                        self.admission.release(r.footprint)
+                        if self.keep_volumes:
+                            r.volume = v.clone()
+                            torch.cuda.current_stream(self.device).synchronize()
+                        self.arena.release(r.offset, r.footprint)
                         done.append(r)
                     inflight[si] = None
-            # admission into a free stream
+            # admission into a free stream (first come, first served)
             free = [si for si, item in enumerate(inflight) if item is None]
             launched = False
             if free and waiting:
@@ -233,9 +305,12 @@ class Server:
                         r.t_plan_ready = time.perf_counter() - t0
                         r.plan_seconds = self.cache.build_seconds.get(key, 0.0)
                         r.footprint = footprint(plan)
+                    off = None
                     if not blocked and len(batch) < self.max_batch and \
-                            (not batch or work < self.group_work) and \
-                            self.admission.try_admit(r.footprint):
+                            (not batch or work < self.group_work):
+                        off = self.arena.alloc(r.footprint)
+                    if off is not None:
+                        r.offset = off
                         r.t_admit = time.perf_counter() - t0
                         batch.append((r, plan))
                         work += float(plan.info["n_vv"])
@@ -245,8 +320,8 @@ class Server:
                 waiting = rest
                 if batch:
                     si = free[0]
-                    ev, vols, held = self._launch(si, batch)
-                    inflight[si] = (ev, batch, vols, held)
+                    ev, vols = self._launch(si, batch)
+                    inflight[si] = (ev, batch, vols)
                     launched = True
             if not launched:
                 time.sleep(0.0002)

@@ -76,7 +76,7 @@ def test_served_results_equal_alone(saturated):
     done = srv.run(rs)
     torch.cuda.synchronize()
     assert len(done) == len(reqs)
-    assert srv.admission.used == 0
+    assert srv.arena.used == 0
     for r in done:
         plan = cache.get_blocking(r.geom, r.grid)
         alone = K.recon(plan, r.sino)
@@ -97,7 +97,7 @@ def test_admission_budget_smaller_than_two_requests_queues_them():
     biggest = max(serve.footprint(cache.get_blocking(r.geom, r.grid)) for r in rs)
     srv = serve.Server(cache, budget_bytes=biggest, max_batch=8)
     done = srv.run(rs)
-    assert len(done) == 3 and srv.admission.used == 0
+    assert len(done) == 3 and srv.arena.used == 0
     # one request in flight at a time: admissions strictly after earlier completions
     order = sorted(done, key=lambda r: r.t_admit)
     for a, b in zip(order, order[1:]):

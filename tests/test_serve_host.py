@@ -1,23 +1,39 @@
 """Host-side tests of the serving policy (no GPU)."""
 import pytest
 
-from paper_2201_02309_amd.serve import Admission, plan_key
+from paper_2201_02309_amd.serve import Arena, plan_key
 
 
-def test_admission_fcfs_under_budget():
-    a = Admission(100)
-    assert a.try_admit(60)
-    assert not a.try_admit(50)          # would exceed: waits
-    assert a.try_admit(40)
-    a.release(60)
-    assert a.try_admit(50)
-    assert a.used == 90
+def test_arena_first_fit_and_coalescing():
+    a = Arena(100 * 256)
+    x = a.alloc(60 * 256)
+    assert x == 0
+    assert a.alloc(50 * 256) is None            # would exceed: waits
+    y = a.alloc(40 * 256)
+    assert y == 60 * 256 and a.used == 100 * 256
+    a.release(x, 60 * 256)
+    z = a.alloc(50 * 256)                       # first fit in the freed range
+    assert z == 0 and a.used == 90 * 256
+    a.release(y, 40 * 256)
+    a.release(z, 50 * 256)
+    assert a.free == [(0, 100 * 256)] and a.used == 0   # fully coalesced
 
 
-def test_admission_rejects_request_larger_than_budget():
-    a = Admission(10)
+def test_arena_rounds_to_256_bytes_and_fragments():
+    a = Arena(4 * 256)
+    p = [a.alloc(1) for _ in range(4)]          # 1 byte takes one 256-byte unit
+    assert p == [0, 256, 512, 768] and a.alloc(1) is None
+    a.release(p[1], 1)
+    a.release(p[3], 1)
+    assert a.alloc(512) is None                 # two free units, not contiguous
+    a.release(p[2], 1)
+    assert a.alloc(512) == 256
+
+
+def test_arena_rejects_request_larger_than_budget():
+    a = Arena(10 * 256)
     with pytest.raises(ValueError):
-        a.try_admit(11)
+        a.alloc(11 * 256)
 
 
 def test_plan_key_distinguishes_geometries():
