@@ -77,8 +77,7 @@ KParams make_params(const PlanHost &P) {
     const unsigned char *base = static_cast<const unsigned char *>(P.d_tables);
     const TableLayout &L = P.layout;
     k.view = reinterpret_cast<const float4 *>(base + L.view);
-    k.fr_row = reinterpret_cast<const int *>(base + L.fr_row);
-    k.fr_w = reinterpret_cast<const float *>(base + L.fr_w);
+    k.fr = reinterpret_cast<const FrEntry *>(base + L.fr);
     k.br_k = reinterpret_cast<const int *>(base + L.br_k);
     k.br_w = reinterpret_cast<const float *>(base + L.br_w);
     k.lw = reinterpret_cast<const float *>(base + L.lw);

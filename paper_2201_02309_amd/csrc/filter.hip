@@ -146,17 +146,38 @@ struct FftShape {
     static_assert(LOG2N >= 6 && LOG2N <= 11, "fft length 64 .. 2048");
 };
 
+// Twiddles w^j, j = 1 .. R-1, of w = tw[step] (conjugated for the inverse): the powers
+// 1, 2, 4, 8 come from the table, the others are products of at most three of them (a few
+// ulp), which trades table reads (latency) for cheap VALU.
+template <int R, bool INV>
+__device__ inline void twiddles(const float2 *__restrict__ tw, int step, float2 *w) {
+    auto ld = [&](int e) { const float2 x = tw[e * step]; return INV ? conj2(x) : x; };
+    w[1] = ld(1);
+    if constexpr (R > 2) {
+        w[2] = ld(2);
+        w[3] = cmul(w[2], w[1]);
+    }
+    if constexpr (R > 4) {
+        w[4] = ld(4);
+#pragma unroll
+        for (int j = 5; j < 8; ++j) w[j] = cmul(w[4], w[j - 4]);
+    }
+    if constexpr (R > 8) {
+        w[8] = ld(8);
+#pragma unroll
+        for (int j = 9; j < 16; ++j) w[j] = cmul(w[8], w[j - 8]);
+    }
+}
+
 // A middle radix-16 pass of span L on this thread's butterfly i = t: twiddles then DFT.
 template <int LOG2N, bool INV>
 __device__ inline void pass16(float2 *v, int t, int L, const float2 *__restrict__ tw) {
     constexpr int N = FftShape<LOG2N>::N;
     const int k = t % L;
-    const int step = k * (N / (16 * L));
+    float2 w[16];
+    twiddles<16, INV>(tw, k * (N / (16 * L)), w);
 #pragma unroll
-    for (int j = 1; j < 16; ++j) {
-        const float2 w = tw[j * step];
-        v[j] = cmul(v[j], INV ? conj2(w) : w);
-    }
+    for (int j = 1; j < 16; ++j) v[j] = cmul(v[j], w[j]);
     dft<16, INV>(v);
 }
 
@@ -184,8 +205,9 @@ __global__ __launch_bounds__(kFftThreads) void k_hilbert_fft(KParams p, const fl
     float *row = g4 + (size_t)i * p.n_psi * cols;                     // output / in-place rows
     const float *v2 = g2 + (size_t)i * rows * cols;
     auto rebin = [&](int k, int c) -> float {
-        const int r0 = p.fr_row[k * cols + c];
-        const float w = p.fr_w[k * cols + c];
+        const FrEntry e = p.fr[k * cols + c];
+        const int r0 = e.r0;
+        const float w = e.w;
         const float x0 = (r0 >= 0 && r0 < rows) ? v2[r0 * cols + c] : 0.0f;
         const float x1 = (r0 + 1 >= 0 && r0 + 1 < rows) ? v2[(r0 + 1) * cols + c] : 0.0f;
         return (1.0f - w) * x0 + w * x1;
@@ -258,11 +280,12 @@ __global__ __launch_bounds__(kFftThreads) void k_hilbert_fft(KParams p, const fl
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int ib = t + T * b;
+        float2 w[RF];
+        twiddles<RF, true>(tw, ib * (N / (RF * L)), w);
 #pragma unroll
         for (int j = 0; j < RF; ++j) {
-            float2 x = X[fft_swz(ib + j * (N / RF))];
-            if (j > 0) x = cmul(x, conj2(tw[j * ib * (N / (RF * L))]));
-            v[b * RF + j] = x;
+            const float2 x = X[fft_swz(ib + j * (N / RF))];
+            v[b * RF + j] = j > 0 ? cmul(x, w[j]) : x;
         }
         dft<RF, true>(v + b * RF);
         if (live) {
@@ -353,8 +376,9 @@ __global__ __launch_bounds__(kElemThreads) void k_fr_lw_T(KParams p, const float
     float *dst = g2bar + (size_t)i * p.rows * p.cols;
     for (int r = 0; r < p.rows; ++r) dst[r * p.cols + c] = 0.0f;
     for (int k = 0; k < p.n_psi; ++k) {
-        const int r0 = p.fr_row[k * p.cols + c];
-        const float t = p.fr_w[k * p.cols + c];
+        const FrEntry e = p.fr[k * p.cols + c];
+        const int r0 = e.r0;
+        const float t = e.w;
         const float v = src[k * p.cols + c];
         if (r0 >= 0 && r0 < p.rows) dst[r0 * p.cols + c] += (1.0f - t) * v;
         if (r0 + 1 >= 0 && r0 + 1 < p.rows) dst[(r0 + 1) * p.cols + c] += t * v;

@@ -25,8 +25,7 @@ struct KParams {
     long long n_views, first_view, n_filt;
     // device tables (inside the caller's bound table buffer)
     const float4 *view;
-    const int *fr_row;
-    const float *fr_w;
+    const FrEntry *fr;
     const int *br_k;
     const float *br_w;
     const float *lw;

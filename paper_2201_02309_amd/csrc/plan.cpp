@@ -481,8 +481,7 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
     L.view = take((uint64_t)P.W * 16);
-    L.fr_row = take((uint64_t)P.n_psi * cols * 4);
-    L.fr_w = take((uint64_t)P.n_psi * cols * 4);
+    L.fr = take((uint64_t)P.n_psi * cols * sizeof(FrEntry));
     L.br_k = take((uint64_t)rows * cols * 4);
     L.br_w = take((uint64_t)rows * cols * 4);
     L.lw = take((uint64_t)rows * 4);
@@ -514,10 +513,9 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
             v[4 * m + 3] = 0.0f;
         }
     }
-    std::memcpy(img + L.fr_row, P.fr_row.data(), P.fr_row.size() * 4);
     {
-        float *d = reinterpret_cast<float *>(img + L.fr_w);
-        for (size_t i = 0; i < P.fr_w.size(); ++i) d[i] = (float)P.fr_w[i];
+        FrEntry *d = reinterpret_cast<FrEntry *>(img + L.fr);
+        for (size_t i = 0; i < P.fr_w.size(); ++i) d[i] = FrEntry{P.fr_row[i], (float)P.fr_w[i]};
     }
     std::memcpy(img + L.br_k, P.br_k.data(), P.br_k.size() * 4);
     {

@@ -47,11 +47,17 @@ struct BpBox {
 };
 static_assert(sizeof(BpBox) == 8, "BpBox must be 8 bytes");
 
+// Forward height rebinning of one (kappa-line, column): rows r0, r0+1 with weight w on r0+1.
+struct FrEntry {
+    int32_t r0;
+    float w;
+};
+static_assert(sizeof(FrEntry) == 8, "FrEntry must be 8 bytes");
+
 // Byte offsets of the sub-tables inside the caller's device table buffer.
 struct TableLayout {
     uint64_t view = 0;       // float4 [W]   cos(beta), sin(beta), e_m, 0
-    uint64_t fr_row = 0;     // int32  [n_psi][cols]
-    uint64_t fr_w = 0;       // float  [n_psi][cols]
+    uint64_t fr = 0;         // FrEntry [n_psi][cols]  forward-rebin row and weight
     uint64_t br_k = 0;       // int32  [rows][cols]
     uint64_t br_w = 0;       // float  [rows][cols]
     uint64_t lw = 0;         // float  [rows]
