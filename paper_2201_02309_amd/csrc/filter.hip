@@ -17,22 +17,35 @@ namespace {
 constexpr int kElemThreads = 256;
 constexpr int kFftThreads = 256;
 
+constexpr int kDerivRun = 32;     // filtered views per thread in k_deriv_lw
+
+// One thread per (detector row, column) walks a run of consecutive views, so each
+// sinogram sample comes from HBM once: the previous / current / next views stay in
+// registers and the neighbouring columns of the current view hit the cache.
 __global__ __launch_bounds__(kElemThreads) void k_deriv_lw(KParams p, const float *__restrict__ sino,
                                                            float *__restrict__ g2) {
-    const long long i = blockIdx.x;                 // filtered view index
+    const int c = blockIdx.x * kElemThreads + threadIdx.x;
     const int r = blockIdx.y;
-    const int c = blockIdx.z * kElemThreads + threadIdx.x;
+    const long long i0 = (long long)blockIdx.z * kDerivRun;   // first filtered view of the run
     if (c >= p.cols) return;
-    const long long n = p.first_view + i;           // 1 <= n <= n_views-2 by construction
+    const long long i1 = i0 + kDerivRun < p.n_filt ? i0 + kDerivRun : p.n_filt;
     const size_t rc = (size_t)p.rows * p.cols;
-    const float *gm = sino + (size_t)(n - 1) * rc + (size_t)r * p.cols;
-    const float *g0 = gm + rc;
-    const float *gp = g0 + rc;
-    const float dl = (gp[c] - gm[c]) * p.inv_2dlam;
-    const float left = c > 0 ? g0[c - 1] : 0.0f;
-    const float right = c + 1 < p.cols ? g0[c + 1] : 0.0f;
-    const float da = (right - left) * p.inv_2dalpha;
-    g2[(size_t)i * rc + (size_t)r * p.cols + c] = p.lw[r] * (dl + da);
+    const float *col = sino + (size_t)r * p.cols + c;         // sample (view 0, r, c)
+    const float w = p.lw[r];
+    long long n = p.first_view + i0;                           // 1 <= n <= n_views-2
+    float prev = col[(size_t)(n - 1) * rc];
+    float cur = col[(size_t)n * rc];
+    for (long long i = i0; i < i1; ++i, ++n) {
+        const float next = col[(size_t)(n + 1) * rc];
+        const float *g0 = col + (size_t)n * rc;
+        const float left = c > 0 ? g0[-1] : 0.0f;
+        const float right = c + 1 < p.cols ? g0[1] : 0.0f;
+        const float dl = (next - prev) * p.inv_2dlam;
+        const float da = (right - left) * p.inv_2dalpha;
+        g2[(size_t)i * rc + (size_t)r * p.cols + c] = w * (dl + da);
+        prev = cur;
+        cur = next;
+    }
 }
 
 __device__ inline float2 cmul(float2 a, float2 b) {
@@ -319,26 +332,31 @@ void launch_hilbert(const KParams &k, const float *g2, float *g4, hipStream_t s)
     }
 }
 
-// Writes the zero-padded view [gf_rows][gf_cols] (border = 0).
+// Writes the zero-padded view [gf_rows][gf_cols] (border = 0).  One thread per (view,
+// padded column) walks the rows: successive rows use neighbouring kappa-lines of the same
+// column (psi_hat rises with w), which the cache keeps, so g4 is read about once.
 __global__ __launch_bounds__(kElemThreads) void k_br_cos(KParams p, const float *__restrict__ g4,
                                                          float *__restrict__ gF) {
-    const long long i = blockIdx.x;
-    const int rp = blockIdx.y;
-    const int cp = blockIdx.z * kElemThreads + threadIdx.x;
+    const long long i = blockIdx.y;
+    const int cp = blockIdx.x * kElemThreads + threadIdx.x;
     const int pitch = p.gf_cols;
     if (cp >= pitch) return;
-    const int r = rp - kPad, c = cp - kPad;
-    float out = 0.0f;
-    if ((unsigned)r < (unsigned)p.rows && (unsigned)c < (unsigned)p.cols) {
-        const int e = r * p.cols + c;
-        const int k0 = p.br_k[e];
-        const float t = p.br_w[e];
-        const float *v4 = g4 + (size_t)i * p.n_psi * p.cols;
-        const float a = v4[k0 * p.cols + c];
-        const float b = v4[(k0 + 1) * p.cols + c];
-        out = p.cos_alpha[c] * ((1.0f - t) * a + t * b);
+    const int c = cp - kPad;
+    const bool incol = (unsigned)c < (unsigned)p.cols;
+    float *out = gF + (size_t)i * p.gf_rows * pitch + cp;
+    const float *v4 = g4 + (size_t)i * p.n_psi * p.cols + c;
+    const float ca = incol ? p.cos_alpha[c] : 0.0f;
+    for (int rp = 0; rp < p.gf_rows; ++rp) {
+        const int r = rp - kPad;
+        float o = 0.0f;
+        if (incol && (unsigned)r < (unsigned)p.rows) {
+            const int e = r * p.cols + c;
+            const int k0 = p.br_k[e];
+            const float t = p.br_w[e];
+            o = ca * ((1.0f - t) * v4[k0 * p.cols] + t * v4[(k0 + 1) * p.cols]);
+        }
+        out[(size_t)rp * pitch] = o;
     }
-    gF[((size_t)i * p.gf_rows + rp) * pitch + cp] = out;
 }
 
 // ----------------------------------------------------------------------------- adjoint
@@ -412,12 +430,11 @@ hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *
                          hipStream_t s) {
     if (k.n_filt <= 0) return hipSuccess;
     const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
-    hipLaunchKernelGGL(k_deriv_lw, dim3((unsigned)k.n_filt, k.rows, cb), dim3(kElemThreads), 0, s,
-                       k, sino, g2);
+    const unsigned runs = (unsigned)((k.n_filt + kDerivRun - 1) / kDerivRun);
+    hipLaunchKernelGGL(k_deriv_lw, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
     launch_hilbert<false>(k, g2, g4, s);
     const int cbp = (k.gf_cols + kElemThreads - 1) / kElemThreads;
-    hipLaunchKernelGGL(k_br_cos, dim3((unsigned)k.n_filt, k.gf_rows, cbp), dim3(kElemThreads),
-                       0, s, k, g4, gF);
+    hipLaunchKernelGGL(k_br_cos, dim3(cbp, (unsigned)k.n_filt), dim3(kElemThreads), 0, s, k, g4, gF);
     return hipGetLastError();
 }
 
