@@ -106,7 +106,8 @@ struct BpShared {
 // Shared by the one-plan kernel (task = block index) and the packed multi-plan kernel.
 // FB: some box of the plan may exceed the LDS tile (those views read their taps from HBM);
 // without it the view loop has a single path, which keeps the accumulators in place.
-template <int KZ, bool FB>
+// P4: the plan's atan polynomial has degree <= 4 in t^2 (otherwise degree 8, or atan2f).
+template <int KZ, bool FB, bool P4>
 __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__restrict__ vol,
                         const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
                         int bxi, int byi, int bz, BpShared &S) {
@@ -258,19 +259,13 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
         const float vinv = __builtin_amdgcn_rcpf(v);
         const float rinv = __builtin_amdgcn_rsqf(fmaf(u, u, v * v));
         float acol;                                          // alpha* / dalpha
-        if (p.atan_deg >= 0) {
+        if (P4 || p.atan_deg >= 0) {
             const float t = u * vinv;                        // tan(alpha*)
             const float s2 = t * t;
-            float qa;
-            if (p.atan_deg <= 4) {                           // uniform: the plan's degree
-                qa = p.atan_coef[4];
+            constexpr int deg = P4 ? 4 : 8;
+            float qa = p.atan_coef[deg];
 #pragma unroll
-                for (int k = 3; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
-            } else {
-                qa = p.atan_coef[8];
-#pragma unroll
-                for (int k = 7; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
-            }
+            for (int k = deg - 1; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
             acol = t * qa;
         } else {
             acol = atan2f(u, v) * p.inv_dalpha;
@@ -337,13 +332,13 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
     }
 }
 
-template <int KZ, bool FB>
+template <int KZ, bool FB, bool P4>
 __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restrict__ gF,
                                                 float *__restrict__ vol,
                                                 const float4 *__restrict__ view_tab,
                                                 const uint2 *__restrict__ box_tab) {
     __shared__ BpShared S;
-    bp_tile<KZ, FB>(p, gF, vol, view_tab, box_tab, blockIdx.x, blockIdx.y, blockIdx.z, S);
+    bp_tile<KZ, FB, P4>(p, gF, vol, view_tab, box_tab, blockIdx.x, blockIdx.y, blockIdx.z, S);
 }
 
 // ---------------------------------------------------------------------------------
@@ -370,7 +365,7 @@ struct BpGroup {
 };
 static_assert(sizeof(BpGroup) <= 4000, "kernel argument segment");
 
-template <int KZ, bool FB>
+template <int KZ, bool FB, bool P4>
 __global__ __launch_bounds__(kNT) void k_bp_group(const BpGroup g) {
     __shared__ BpShared S;
     const long long task = blockIdx.x;
@@ -382,7 +377,7 @@ __global__ __launch_bounds__(kNT) void k_bp_group(const BpGroup g) {
     local /= q.a.tiles_x;
     const int byi = (int)(local % q.a.tiles_y);
     const int bz = (int)(local / q.a.tiles_y);
-    bp_tile<KZ, FB>(q.a, q.gF, q.vol, q.view, q.boxes, bxi, byi, bz, S);
+    bp_tile<KZ, FB, P4>(q.a, q.gF, q.vol, q.view, q.boxes, bxi, byi, bz, S);
 }
 
 // ---------------------------------------------------------------------------------
@@ -510,46 +505,66 @@ static BpArgs bp_args(const KParams &k) {
     return a;
 }
 
+// Kernel instance of a plan: bit 0 = HBM fallback path, bit 1 = short atan polynomial.
+static int kernel_class(const KParams &k) {
+    return (k.bp_all_fit ? 0 : 1) | ((k.atan_deg >= 0 && k.atan_deg <= 4) ? 2 : 0);
+}
+
+template <int KZ>
+static void launch_lds(int cls, dim3 grid, hipStream_t s, const BpArgs &a, const float *gF,
+                       float *vol, const float4 *view, const uint2 *boxes) {
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((k_bp_lds<KZ, false, false>), grid, dim3(kNT), 0, s, a, gF, vol, view, boxes); break;
+        case 1: hipLaunchKernelGGL((k_bp_lds<KZ, true, false>), grid, dim3(kNT), 0, s, a, gF, vol, view, boxes); break;
+        case 2: hipLaunchKernelGGL((k_bp_lds<KZ, false, true>), grid, dim3(kNT), 0, s, a, gF, vol, view, boxes); break;
+        default: hipLaunchKernelGGL((k_bp_lds<KZ, true, true>), grid, dim3(kNT), 0, s, a, gF, vol, view, boxes); break;
+    }
+}
+
+template <int KZ>
+static void launch_group(int cls, dim3 grid, hipStream_t s, const BpGroup &g) {
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((k_bp_group<KZ, false, false>), grid, dim3(kNT), 0, s, g); break;
+        case 1: hipLaunchKernelGGL((k_bp_group<KZ, true, false>), grid, dim3(kNT), 0, s, g); break;
+        case 2: hipLaunchKernelGGL((k_bp_group<KZ, false, true>), grid, dim3(kNT), 0, s, g); break;
+        default: hipLaunchKernelGGL((k_bp_group<KZ, true, true>), grid, dim3(kNT), 0, s, g); break;
+    }
+}
+
 hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s) {
     dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
     const BpArgs a = bp_args(k);
     const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
-#define KATS_BP_LAUNCH(KZ, FB) \
-    hipLaunchKernelGGL((k_bp_lds<KZ, FB>), grid, dim3(kNT), 0, s, a, gF, vol, k.view, boxes)
-    const bool fb = !k.bp_all_fit;
+    const int cls = kernel_class(k);
     switch (k.bp_kz) {
-        case 8: if (fb) KATS_BP_LAUNCH(8, true); else KATS_BP_LAUNCH(8, false); break;
-        case 32: if (fb) KATS_BP_LAUNCH(32, true); else KATS_BP_LAUNCH(32, false); break;
-        default: if (fb) KATS_BP_LAUNCH(16, true); else KATS_BP_LAUNCH(16, false); break;
+        case 8: launch_lds<8>(cls, grid, s, a, gF, vol, k.view, boxes); break;
+        case 32: launch_lds<32>(cls, grid, s, a, gF, vol, k.view, boxes); break;
+        default: launch_lds<16>(cls, grid, s, a, gF, vol, k.view, boxes); break;
     }
-#undef KATS_BP_LAUNCH
     return hipGetLastError();
 }
 
-// Requests whose boxes all fit the LDS tile run in launches without the HBM path, the
-// others in launches with it; each launch takes up to kGroupMax requests.
+// Requests are grouped by kernel instance (HBM fallback path or not, atan polynomial
+// length); each launch takes up to kGroupMax requests of one class.
 hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, float *const *vol,
                                     int n, int kz, hipStream_t s) {
-    for (int pass = 0; pass < 2; ++pass) {
-        const bool fb = pass == 1;
+    for (int cls = 0; cls < 4; ++cls) {
         BpGroup grp{};
         long long total = 0;
         auto flush = [&]() {
             if (grp.n == 0) return;
             const dim3 grid((unsigned)total);
-#define KATS_BPG_LAUNCH(KZ, FB) hipLaunchKernelGGL((k_bp_group<KZ, FB>), grid, dim3(kNT), 0, s, grp)
             switch (kz) {
-                case 8: if (fb) KATS_BPG_LAUNCH(8, true); else KATS_BPG_LAUNCH(8, false); break;
-                case 32: if (fb) KATS_BPG_LAUNCH(32, true); else KATS_BPG_LAUNCH(32, false); break;
-                default: if (fb) KATS_BPG_LAUNCH(16, true); else KATS_BPG_LAUNCH(16, false); break;
+                case 8: launch_group<8>(cls, grid, s, grp); break;
+                case 32: launch_group<32>(cls, grid, s, grp); break;
+                default: launch_group<16>(cls, grid, s, grp); break;
             }
-#undef KATS_BPG_LAUNCH
             grp = BpGroup{};
             total = 0;
         };
         for (int i = 0; i < n; ++i) {
             const KParams &k = ks[i];
-            if ((k.bp_all_fit == 0) != fb) continue;
+            if (kernel_class(k) != cls) continue;
             const long long tasks = (long long)k.bp_tiles_x * k.bp_tiles_y * k.n_pitches * k.bp_runs;
             if (tasks == 0) continue;
             if (grp.n == kGroupMax || total + tasks > 0x7fffffffLL) flush();
