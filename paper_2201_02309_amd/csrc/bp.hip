@@ -70,8 +70,10 @@ __device__ inline T ldg(const T *ptr) {
 constexpr int kT = kBpTile;       // 16
 constexpr int kNT = kT * kT;      // 256 lanes
 constexpr int kLP = kBpBoxCols;   // LDS tile row pitch (floats) = max box columns
-constexpr int kLR = kBpBoxRows;   // max box rows
-constexpr int kLMax = kLP * kLR;  // 2048 floats per buffer
+// LDS tile depth (max box rows) of a slice run: runs of 32 slices span up to ~60 detector
+// rows, shorter runs fit 32.
+template <int KZ>
+constexpr int lds_rows() { return KZ >= 32 ? 2 * kBpBoxRows : kBpBoxRows; }
 constexpr int kHull = 2048;       // max views of a workgroup hull with per-view group words
 constexpr int kKG = 4;            // slices per branch group
 
@@ -96,8 +98,9 @@ __device__ inline float lerp_bilinear(P t, int pitch_f, float tc, float tr) {
 }
 
 // Shared memory of one backprojection workgroup.
+template <int KZ>
 struct BpShared {
-    __attribute__((aligned(16))) float tile[2][kLMax];   // double-buffered footprint box
+    __attribute__((aligned(16))) float tile[2][kLP * lds_rows<KZ>()];   // double-buffered box
     unsigned short words[4][kHull];  // per wave and view: active groups | full groups << 8
     int red[8];
 };
@@ -110,9 +113,11 @@ struct BpShared {
 template <int KZ, bool FB, bool P4>
 __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__restrict__ vol,
                         const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
-                        int bxi, int byi, int bz, BpShared &S) {
+                        int bxi, int byi, int bz, BpShared<KZ> &S) {
     static_assert(KZ % kKG == 0 && KZ / kKG <= 8, "groups use 8-bit masks");
-    static_assert(kLR == 32, "box staging covers 32 rows with two 16-row passes");
+    constexpr int kLR = lds_rows<KZ>();
+    constexpr int NP = kLR / 16;          // staging passes of 16 rows x 16 float4 lanes
+    static_assert(NP == 2 || NP == 4, "box staging passes");
     constexpr int NG = KZ / kKG;
     auto &lds = S.tile;
     auto &words = S.words;
@@ -221,12 +226,11 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
         if (mlo < mhi) bw_next = ldg(boxes + mlo + 1);
         if (fits(b)) {
             const float *src = gF0 + (size_t)mlo * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad);
-            if (srow < b.nr && scol < b.nc)
-                *reinterpret_cast<float4 *>(&lds[0][srow * kLP + scol]) =
-                    ldg(reinterpret_cast<const float4 *>(src + srow * cpitch + scol));
-            if (srow + 16 < b.nr && scol < b.nc)
-                *reinterpret_cast<float4 *>(&lds[0][(srow + 16) * kLP + scol]) =
-                    ldg(reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol));
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                if (srow + 16 * k < b.nr && scol < b.nc)
+                    *reinterpret_cast<float4 *>(&lds[0][(srow + 16 * k) * kLP + scol]) =
+                        ldg(reinterpret_cast<const float4 *>(src + (srow + 16 * k) * cpitch + scol));
         }
     }
     __syncthreads();
@@ -236,19 +240,22 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
         // box of view m+2, loaded one iteration ahead of its use
         uint2 bw_after = make_uint2(0u, 0u);
         if (m + 2 <= mhi) bw_after = ldg(boxes + m + 2);
-        // prefetch the next view's box into registers (two rows of 16 float4 lanes)
-        float4 pf0, pf1;
+        // prefetch the next view's box into registers (NP rows of 16 float4 lanes)
+        float4 pf[NP];
         BpBox bn = b;
-        bool next_fits = false, st0 = false, st1 = false;
+        bool next_fits = false, stg[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) stg[k] = false;
         if (m < mhi) {
             bn = unpack(bw_next);
             next_fits = fits(bn);
             if (next_fits) {
                 const float *src = gF0 + (size_t)(m + 1) * vstride + (bn.r0 + kPad) * cpitch + (bn.c0 + kPad);
-                st0 = srow < bn.nr && scol < bn.nc;
-                st1 = srow + 16 < bn.nr && scol < bn.nc;
-                if (st0) pf0 = ldg(reinterpret_cast<const float4 *>(src + srow * cpitch + scol));
-                if (st1) pf1 = ldg(reinterpret_cast<const float4 *>(src + (srow + 16) * cpitch + scol));
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    stg[k] = srow + 16 * k < bn.nr && scol < bn.nc;
+                    if (stg[k]) pf[k] = ldg(reinterpret_cast<const float4 *>(src + (srow + 16 * k) * cpitch + scol));
+                }
             }
         }
         // per (lane, view) geometry; coordinates relative to the box origin, clamped into
@@ -315,8 +322,9 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
         }
         {
             float *Dst = lds[buf ^ 1];
-            if (st0) *reinterpret_cast<float4 *>(&Dst[srow * kLP + scol]) = pf0;
-            if (st1) *reinterpret_cast<float4 *>(&Dst[(srow + 16) * kLP + scol]) = pf1;
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                if (stg[k]) *reinterpret_cast<float4 *>(&Dst[(srow + 16 * k) * kLP + scol]) = pf[k];
         }
         b = bn;
         bw_next = bw_after;
@@ -337,7 +345,7 @@ __global__ __launch_bounds__(kNT) void k_bp_lds(BpArgs p, const float *__restric
                                                 float *__restrict__ vol,
                                                 const float4 *__restrict__ view_tab,
                                                 const uint2 *__restrict__ box_tab) {
-    __shared__ BpShared S;
+    __shared__ BpShared<KZ> S;
     bp_tile<KZ, FB, P4>(p, gF, vol, view_tab, box_tab, blockIdx.x, blockIdx.y, blockIdx.z, S);
 }
 
@@ -367,7 +375,7 @@ static_assert(sizeof(BpGroup) <= 4000, "kernel argument segment");
 
 template <int KZ, bool FB, bool P4>
 __global__ __launch_bounds__(kNT) void k_bp_group(const BpGroup g) {
-    __shared__ BpShared S;
+    __shared__ BpShared<KZ> S;
     const long long task = blockIdx.x;
     int r = 0;
     while (r + 1 < g.n && g.r[r + 1].first_task <= task) ++r;

@@ -90,7 +90,7 @@ KParams make_params(const PlanHost &P) {
     k.bp_tiles_y = P.bp_tiles_y;
     k.bp_runs = P.bp_runs;
     k.bp_kz = P.bp_kz;
-    k.bp_all_fit = P.bp_box_rows <= kBpBoxRows && P.bp_box_cols <= kBpBoxCols;
+    k.bp_all_fit = P.bp_box_rows <= (P.bp_kz >= 32 ? 2 : 1) * kBpBoxRows && P.bp_box_cols <= kBpBoxCols;
     k.gf_rows = P.gf_rows;
     k.gf_cols = P.gf_cols;
     k.atan_deg = P.atan_deg;
