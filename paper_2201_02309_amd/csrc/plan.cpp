@@ -98,7 +98,9 @@ struct PiSolver {
             if (!(der > 0.0)) return false;
             const double sn = s - f / der;
             if (!(sn > zr - kTwoPi && sn < zr)) return false;
-            if (std::fabs(sn - s) <= 2e-16 * std::max(1.0, std::fabs(s))) { root = sn; return true; }
+            // quadratic convergence: after a step of 1e-9 the error is ~1e-18, below the
+            // float64 resolution of s, so the update is final
+            if (std::fabs(sn - s) <= 1e-9 * std::max(1.0, std::fabs(s))) { root = sn; return true; }
             s = sn;
         }
         return false;
@@ -436,18 +438,33 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     P.n_vv = 0;
     P.n_valid = 0;
     int64_t vmin = std::numeric_limits<int64_t>::max(), vmax = std::numeric_limits<int64_t>::min();
-    for (int iz = 0; iz < gr.nz; ++iz) {
-        const int k = iz / P.ns, j = iz % P.ns;
-        const int64_t shift = (int64_t)k * g.views_per_turn;
-        for (size_t q = 0; q < plane; ++q) {
-            const size_t e = (size_t)j * plane + q;
-            if (!P.fov[e]) continue;
-            const int64_t nf = P.pi_nf[e] + shift, nl = P.pi_nl[e] + shift;
-            if (nf - 1 < 0 || nl + 1 > g.n_views - 1) continue;
-            P.n_valid += 1;
-            P.n_vv += nl - nf + 1;
-            vmin = std::min(vmin, nf);
-            vmax = std::max(vmax, nl);
+    {
+        struct Part {
+            int64_t n_vv = 0, n_valid = 0;
+            int64_t vmin = std::numeric_limits<int64_t>::max();
+            int64_t vmax = std::numeric_limits<int64_t>::min();
+        };
+        std::vector<Part> part((size_t)gr.nz);          // one per slice, summed in order
+        parallel_for(gr.nz, threads_for(opts), [&](int iz) {
+            const int k = iz / P.ns, j = iz % P.ns;
+            const int64_t shift = (int64_t)k * g.views_per_turn;
+            Part &pt = part[(size_t)iz];
+            for (size_t q = 0; q < plane; ++q) {
+                const size_t e = (size_t)j * plane + q;
+                if (!P.fov[e]) continue;
+                const int64_t nf = P.pi_nf[e] + shift, nl = P.pi_nl[e] + shift;
+                if (nf - 1 < 0 || nl + 1 > g.n_views - 1) continue;
+                pt.n_valid += 1;
+                pt.n_vv += nl - nf + 1;
+                pt.vmin = std::min(pt.vmin, nf);
+                pt.vmax = std::max(pt.vmax, nl);
+            }
+        });
+        for (const Part &pt : part) {
+            P.n_valid += pt.n_valid;
+            P.n_vv += pt.n_vv;
+            vmin = std::min(vmin, pt.vmin);
+            vmax = std::max(vmax, pt.vmax);
         }
     }
     if (P.n_valid == 0) {
