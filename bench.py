@@ -186,6 +186,11 @@ def main():
     t0 = time.perf_counter()
     plan = K.Plan(geom, gr, device=0, bp_slices=args.bp_slices)
     t_plan = time.perf_counter() - t0
+    # the same plan with the PI lines solved on the GPU (katsevich_plan_device); warmed once
+    K.Plan(geom, gr, bind=False, gpu_plan=True, device=0, bp_slices=args.bp_slices).close()
+    t0 = time.perf_counter()
+    K.Plan(geom, gr, bind=False, gpu_plan=True, device=0, bp_slices=args.bp_slices).close()
+    t_plan_gpu = time.perf_counter() - t0
     info = plan.info
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
     sino = gpu_projector.project(ph, geom, device=dev)          # whole scan, resident in HBM
@@ -261,6 +266,7 @@ def main():
         "stage_ms": {"filter": round(float(np.mean(filt_ms)), 4), "backproject": round(bp_avg, 4)},
         "recon_call_ms": round(recon_ms, 4),
         "plan_build_s": round(t_plan, 3),
+        "plan_build_gpu_pi_s": round(t_plan_gpu, 3),
         "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,

@@ -138,6 +138,21 @@ enum {
 int katsevich_plan(const katsevich_geometry *geom, const katsevich_grid *grid,
                    const katsevich_options *opts, katsevich_plan_t *out);
 
+/* Device scratch (bytes) katsevich_plan_device needs: two float64 per voxel of one
+ * pitch's slices (n_table_slices x ny x nx), 256-byte aligned halves. */
+uint64_t katsevich_plan_device_scratch_bytes(const katsevich_geometry *geom,
+                                             const katsevich_grid *grid);
+
+/* Same plan as katsevich_plan (same tables up to the last bits of the float64 PI limits),
+ * with the PI lines of every voxel of one pitch (pre-calculating step 2 of Sec. II, the
+ * plan's dominant cost) solved on the GPU in float64; everything else is built on the host.
+ * d_scratch: caller device buffer of katsevich_plan_device_scratch_bytes() bytes (256-byte
+ * aligned), free again when the call returns; the call synchronises stream.  Errors as
+ * katsevich_plan, plus KATS_EWORKSPACE (scratch too small) and KATS_EHIP. */
+int katsevich_plan_device(const katsevich_geometry *geom, const katsevich_grid *grid,
+                          const katsevich_options *opts, void *d_scratch, uint64_t scratch_bytes,
+                          void *stream, katsevich_plan_t *out);
+
 /* Sizes and counts of the plan. */
 int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out);
 

@@ -22,7 +22,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 # device code: no packed-FP32 instructions; hardware float atomics
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-SOURCES = [("plan.cpp", False), ("capi.cpp", False), ("filter.hip", True), ("bp.hip", True)]
+SOURCES = [("plan.cpp", False), ("capi.cpp", False), ("filter.hip", True), ("bp.hip", True),
+           ("plan_gpu.hip", True)]
 
 
 def _run(cmd):

@@ -148,6 +148,44 @@ int katsevich_plan(const katsevich_geometry *geom, const katsevich_grid *grid,
     return KATS_OK;
 }
 
+uint64_t katsevich_plan_device_scratch_bytes(const katsevich_geometry *geom,
+                                             const katsevich_grid *grid) {
+    if (!geom || !grid) return 0;
+    return kats::pi_scratch_bytes(*geom, *grid);
+}
+
+int katsevich_plan_device(const katsevich_geometry *geom, const katsevich_grid *grid,
+                          const katsevich_options *opts, void *d_scratch, uint64_t scratch_bytes,
+                          void *stream, katsevich_plan_t *out) {
+    g_err.clear();
+    if (!geom || !grid || !out || !d_scratch)
+        return fail(KATS_EINVAL, "katsevich_plan_device: null argument");
+    *out = nullptr;
+    if (!aligned256(d_scratch)) return fail(KATS_EINVAL, "katsevich_plan_device: scratch not 256-byte aligned");
+    katsevich_options o{};
+    if (opts) o = *opts;
+    katsevich_plan_s *p = new (std::nothrow) katsevich_plan_s();
+    if (!p) return fail(KATS_ENOMEM, "katsevich_plan_device: out of host memory");
+    const kats::DevicePiSolve dev{d_scratch, scratch_bytes, stream};
+    std::string err;
+    int st;
+    try {
+        st = kats::build_plan(*geom, *grid, o, p->P, err, &dev);
+    } catch (const std::bad_alloc &) {
+        st = KATS_ENOMEM;
+        err = "out of host memory while planning";
+    } catch (...) {
+        st = KATS_EINVAL;
+        err = "unexpected failure while planning";
+    }
+    if (st != KATS_OK) {
+        delete p;
+        return fail(st, "katsevich_plan_device: " + err);
+    }
+    *out = p;
+    return KATS_OK;
+}
+
 int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
     g_err.clear();
     if (!plan || !out) return fail(KATS_EINVAL, "katsevich_plan_query: null argument");

@@ -43,6 +43,11 @@ struct KParams {
 
 KParams make_params(const PlanHost &P);
 
+// PI lines (lambda_i, lambda_o) of every voxel of the first n_tab slices, float64, into
+// d_li / d_lo [n_tab][ny][nx].
+hipError_t launch_pi_solve(const katsevich_geometry &g, const katsevich_grid &gr, double h,
+                           int n_tab, double *d_li, double *d_lo, hipStream_t s);
+
 // Forward filter chain on views first_view..last_view:
 //   g2 = deriv+LW(sino); g4 = Hilbert(FR(g2)); gF = cos * BR(g4).
 hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,

@@ -1,5 +1,6 @@
 // Host float64 plan builder: see plan.hpp.
 #include "plan.hpp"
+#include "kernels.hpp"
 
 #include <algorithm>
 #include <atomic>
@@ -264,8 +265,25 @@ bool voxel_valid(const PlanHost &P, int iz, int iy, int ix) {
     return P.pi_nf[e] + shift - 1 >= 0 && P.pi_nl[e] + shift + 1 <= P.geom.n_views - 1;
 }
 
+static int table_slices(const katsevich_geometry &g, const katsevich_grid &gr, int *ns_out,
+                        bool *comm_out) {
+    const int ns_round = (int)std::llround(g.feed_per_turn / gr.dz);
+    const bool comm = ns_round >= 1 && std::fabs(ns_round * gr.dz - g.feed_per_turn) <= 1e-9 * g.feed_per_turn;
+    const int ns = comm ? ns_round : gr.nz;
+    if (ns_out) *ns_out = ns;
+    if (comm_out) *comm_out = comm;
+    return std::min(ns, gr.nz);
+}
+
+uint64_t pi_scratch_bytes(const katsevich_geometry &g, const katsevich_grid &gr) {
+    if (!(gr.dz > 0) || gr.nx < 1 || gr.ny < 1 || gr.nz < 1) return 0;
+    const uint64_t nvox = (uint64_t)table_slices(g, gr, nullptr, nullptr) * gr.ny * gr.nx;
+    return 2 * align256(nvox * sizeof(double));
+}
+
 int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
-               const katsevich_options &opts, PlanHost &P, std::string &err) {
+               const katsevich_options &opts, PlanHost &P, std::string &err,
+               const DevicePiSolve *dev) {
     P.geom = g;
     P.grid = gr;
     P.opts = opts;
@@ -371,15 +389,7 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
     }
 
     // ------------------------------------------------------------------ pitches
-    const int ns_round = (int)std::llround(g.feed_per_turn / gr.dz);
-    if (ns_round >= 1 && std::fabs(ns_round * gr.dz - g.feed_per_turn) <= 1e-9 * g.feed_per_turn) {
-        P.commensurate = true;
-        P.ns = ns_round;
-    } else {
-        P.commensurate = false;
-        P.ns = gr.nz;
-    }
-    P.n_tab = std::min(P.ns, gr.nz);
+    P.n_tab = table_slices(g, gr, &P.ns, &P.commensurate);
     P.n_pitches = (gr.nz + P.ns - 1) / P.ns;
 
     // ------------------------------------------------------------------ PI limits
@@ -395,31 +405,62 @@ int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
         err = "out of host memory for PI tables";
         return KATS_ENOMEM;
     }
-    const PiSolver S{g.R, P.h, g.lambda0, g.z0};
+    if (dev) {
+        // lambda_i, lambda_o on the GPU, copied back into pi_li / pi_lo
+        if (dev->bytes < pi_scratch_bytes(g, gr) || !dev->scratch) {
+            err = "PI-line scratch smaller than the plan needs";
+            return KATS_EWORKSPACE;
+        }
+        double *d_li = static_cast<double *>(dev->scratch);
+        double *d_lo = reinterpret_cast<double *>(static_cast<unsigned char *>(dev->scratch) +
+                                                  align256(nvox * sizeof(double)));
+        hipStream_t st = static_cast<hipStream_t>(dev->stream);
+        hipError_t e = launch_pi_solve(g, gr, P.h, P.n_tab, d_li, d_lo, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(P.pi_li.data(), d_li, nvox * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(P.pi_lo.data(), d_lo, nvox * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            err = std::string("GPU PI-line solve: ") + hipGetErrorString(e);
+            return KATS_EHIP;
+        }
+    } else {
+        const PiSolver S{g.R, P.h, g.lambda0, g.z0};
+        // per voxel column (x, y), slices in increasing z so each root brackets the next
+        const double step = 2.0 * gr.dz / P.h;
+        parallel_for(gr.ny, threads_for(opts), [&](int iy) {
+            const double y = gr.y_first + iy * gr.dy;
+            for (int ix = 0; ix < gr.nx; ++ix) {
+                const double x = gr.x_first + ix * gr.dx;
+                double prev = 0.0, prev2 = 0.0;
+                for (int j = 0; j < P.n_tab; ++j) {
+                    const double z = gr.z_first + j * gr.dz;
+                    const size_t e = (size_t)j * plane + (size_t)iy * gr.nx + ix;
+                    double li, lo;
+                    const double guess = 2.0 * prev - prev2;     // linear extrapolation in z
+                    S.solve(x, y, z, li, lo, j > 0 ? &prev : nullptr, step, j > 1 ? &guess : nullptr);
+                    prev2 = prev;
+                    prev = li;
+                    P.pi_li[e] = li;
+                    P.pi_lo[e] = lo;
+                }
+            }
+        });
+    }
+    // view units, first / last covered views, field of view
     const double r2 = P.r_fov * P.r_fov;
-    // per voxel column (x, y), slices in increasing z so each root brackets the next
-    const double step = 2.0 * gr.dz / P.h;
-    parallel_for(gr.ny, threads_for(opts), [&](int iy) {
+    parallel_for(P.n_tab * gr.ny, threads_for(opts), [&](int jy) {
+        const int iy = jy % gr.ny;
         const double y = gr.y_first + iy * gr.dy;
         for (int ix = 0; ix < gr.nx; ++ix) {
-          const double x = gr.x_first + ix * gr.dx;
-          double prev = 0.0, prev2 = 0.0;
-          for (int j = 0; j < P.n_tab; ++j) {
-            const double z = gr.z_first + j * gr.dz;
-            const size_t e = (size_t)j * plane + (size_t)iy * gr.nx + ix;
-            double li, lo;
-            const double guess = 2.0 * prev - prev2;         // linear extrapolation in z
-            S.solve(x, y, z, li, lo, j > 0 ? &prev : nullptr, step, j > 1 ? &guess : nullptr);
-            prev2 = prev;
-            prev = li;
-            const double vi = (li - g.lambda_first) / P.dlam;
-            const double vo = (lo - g.lambda_first) / P.dlam;
+            const double x = gr.x_first + ix * gr.dx;
+            const size_t e = (size_t)jy * gr.nx + ix;
+            const double vi = (P.pi_li[e] - g.lambda_first) / P.dlam;
+            const double vo = (P.pi_lo[e] - g.lambda_first) / P.dlam;
             P.pi_li[e] = vi;
             P.pi_lo[e] = vo;
             P.pi_nf[e] = (int32_t)(std::floor(vi - 0.5) + 1.0);
             P.pi_nl[e] = (int32_t)(std::ceil(vo + 0.5) - 1.0);
             P.fov[e] = (x * x + y * y <= r2) ? 1 : 0;
-          }
         }
     });
 

@@ -118,9 +118,22 @@ struct PlanHost {
     uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0;   // gF: padded [n][rows+2kPad][cols+2kPad]
 };
 
-// Build the plan; returns a KATS_* status and fills err on failure.
+// Device resources for solving the PI lines on the GPU (scratch of pi_scratch_bytes()).
+struct DevicePiSolve {
+    void *scratch;
+    uint64_t bytes;
+    void *stream;
+};
+
+// Build the plan; returns a KATS_* status and fills err on failure.  With dev, the PI lines
+// of one pitch are solved on the GPU (float64, same iteration) and the rest on the host.
 int build_plan(const katsevich_geometry &g, const katsevich_grid &grid,
-               const katsevich_options &opts, PlanHost &P, std::string &err);
+               const katsevich_options &opts, PlanHost &P, std::string &err,
+               const DevicePiSolve *dev = nullptr);
+
+// Device scratch the GPU PI solve needs for this geometry and grid (two float64 per voxel
+// of one pitch's slices).
+uint64_t pi_scratch_bytes(const katsevich_geometry &g, const katsevich_grid &grid);
 
 // Validity of voxel (iz, iy, ix) (integer decision taken from the float64 tables).
 bool voxel_valid(const PlanHost &P, int iz, int iy, int ix);

@@ -66,7 +66,8 @@ TABLES = {
 EXPORTED = ["katsevich_plan", "katsevich_plan_query", "katsevich_plan_bind",
             "katsevich_plan_export", "katsevich_recon", "katsevich_filter",
             "katsevich_backproject", "katsevich_recon_backward", "katsevich_backproject_batch",
-            "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error"]
+            "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error",
+            "katsevich_plan_device", "katsevich_plan_device_scratch_bytes"]
 
 _lib = None
 
@@ -92,6 +93,11 @@ def load_library(path: str = LIB_PATH):
                                              c_void_p]
     lib.katsevich_backproject_batch.argtypes = [POINTER(c_void_p), POINTER(c_void_p),
                                                 POINTER(c_void_p), c_int, c_void_p]
+    lib.katsevich_plan_device.argtypes = [POINTER(_Geometry), POINTER(_Grid), POINTER(_Options),
+                                          c_void_p, c_uint64, c_void_p, POINTER(c_void_p)]
+    lib.katsevich_plan_device.restype = c_int
+    lib.katsevich_plan_device_scratch_bytes.argtypes = [POINTER(_Geometry), POINTER(_Grid)]
+    lib.katsevich_plan_device_scratch_bytes.restype = c_uint64
     lib.katsevich_plan_destroy.argtypes = [c_void_p]
     lib.katsevich_plan_destroy.restype = None
     lib.katsevich_status_string.argtypes = [c_int]
@@ -138,7 +144,9 @@ class Plan:
     geom / grid: dicts with the fields of katsevich_geometry / katsevich_grid."""
 
     def __init__(self, geom: dict, grid: dict, n_psi: int = 0, n_threads: int = 0,
-                 bind: bool = True, device=None, bp_slices: int = 0):
+                 bind: bool = True, device=None, bp_slices: int = 0, gpu_plan: bool = False):
+        """gpu_plan: solve the PI lines on the GPU (katsevich_plan_device) with a scratch
+        tensor on `device` and its current stream; otherwise everything on the host."""
         self._lib = load_library()
         self.geom = dict(geom)
         self.grid = dict(grid)
@@ -146,8 +154,18 @@ class Plan:
         opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads), flags=0,
                         bp_slices=int(bp_slices))
         g, gr = _geom_struct(geom), _grid_struct(grid)
-        _check(self._lib, self._lib.katsevich_plan(byref(g), byref(gr), byref(opts),
-                                                   byref(self._h)))
+        if gpu_plan:
+            import torch
+            dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+            need = int(self._lib.katsevich_plan_device_scratch_bytes(byref(g), byref(gr)))
+            scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+            _check(self._lib, self._lib.katsevich_plan_device(
+                byref(g), byref(gr), byref(opts), c_void_p(scratch.data_ptr()),
+                c_uint64(scratch.numel()), _stream_handle(dev), byref(self._h)))
+            del scratch
+        else:
+            _check(self._lib, self._lib.katsevich_plan(byref(g), byref(gr), byref(opts),
+                                                       byref(self._h)))
         info = _Info()
         _check(self._lib, self._lib.katsevich_plan_query(self._h, byref(info)))
         self.info = {k: getattr(info, k) for k, _ in _Info._fields_}

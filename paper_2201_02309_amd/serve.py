@@ -3,8 +3,9 @@
 Requests (a scan geometry, a voxel grid and a device-resident sinogram) arrive over time.
 The server
 
-* builds the float64 plan of each new geometry on host worker threads (plans are cached by
-  the exact geometry/grid tuple and bound to device tables once),
+* builds the float64 plan of each new geometry on worker threads (the PI lines on the GPU,
+  the rest on the host; plans are cached by the exact geometry/grid tuple and bound to
+  device tables once),
 * admits ready requests first-come-first-served while their device footprint (sinogram
   copy, filter workspace, g^F, volume) gets a contiguous block of the server's HBM arena
   (one buffer of the budget's size, first-fit), otherwise they wait until earlier requests
@@ -65,9 +66,10 @@ class PlanCache:
     """Plans keyed by geometry; built and bound on worker threads (each worker binds on its
     own stream, so the serving streams never wait for a table upload)."""
 
-    def __init__(self, device, workers=2, n_psi=0, bp_slices=0):
+    def __init__(self, device, workers=2, n_psi=0, bp_slices=0, gpu_plan=True):
         self.device = device
         self.n_psi, self.bp_slices = n_psi, bp_slices
+        self.gpu_plan = gpu_plan                   # PI lines on the GPU (katsevich_plan_device)
         self.plans = {}
         self.pending = {}
         self.build_seconds = {}
@@ -80,14 +82,16 @@ class PlanCache:
     def _build(self, geom, grid):
         import torch
         t0 = time.perf_counter()
-        plan = K.Plan(geom, grid, n_psi=self.n_psi, bind=False, bp_slices=self.bp_slices)
         tid = threading.get_ident()
         with self._lock:
             s = self._streams.get(tid)
             if s is None:
                 s = self._streams[tid] = torch.cuda.Stream(device=self.device)
+        index = self.device.index if hasattr(self.device, "index") else self.device
         with torch.cuda.stream(s):
-            plan.bind(self.device.index if hasattr(self.device, "index") else self.device)
+            plan = K.Plan(geom, grid, n_psi=self.n_psi, bind=False, bp_slices=self.bp_slices,
+                          gpu_plan=self.gpu_plan, device=index)
+            plan.bind(index)
         return plan, time.perf_counter() - t0
 
     def request(self, geom, grid):
