@@ -238,6 +238,18 @@ def main():
     torch.cuda.synchronize()
     recon_ms = (time.perf_counter() - t1) * 1e3 / max(3, args.steps // 2)
 
+    # the adjoint (katsevich_recon_backward: sinogram cotangent of a volume cotangent)
+    gvol = torch.randn_like(vol)
+    gsino = torch.empty_like(sino)
+    K.recon_backward(plan, gvol, out=gsino, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        K.recon_backward(plan, gvol, out=gsino, ws=ws)
+    torch.cuda.synchronize()
+    adjoint_ms = (time.perf_counter() - t1) * 1e3 / 3
+    del gvol, gsino
+
     bp_avg = float(np.mean(bp_ms))
     achieved = n_vv * BP_FLOP_PER_UPDATE / (bp_avg * 1e-3) / 1e12
     traffic = _measured_traffic()
@@ -265,6 +277,7 @@ def main():
         "volumes_per_s": round(1e3 / ms_step, 3),
         "stage_ms": {"filter": round(float(np.mean(filt_ms)), 4), "backproject": round(bp_avg, 4)},
         "recon_call_ms": round(recon_ms, 4),
+        "adjoint_call_ms": round(adjoint_ms, 3),
         "plan_build_s": round(t_plan, 3),
         "plan_build_gpu_pi_s": round(t_plan_gpu, 3),
         "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": round(achieved, 3),

@@ -1,0 +1,333 @@
+// Adjoint of the backprojection (the transpose of the operator in bp.hip), for the
+// gradient of a reconstruction loss with respect to the filtered data.
+#include "bp_common.hpp"
+
+namespace kats {
+
+namespace {
+
+using namespace bpdev;
+
+// ---------------------------------------------------------------------------------
+// Adjoint of the backprojection, tiled like the forward kernel: the workgroup's 16 x 16
+// voxel columns x KZ slices, the same PI-window hull, group words and footprint boxes.  At
+// each view every lane scatters its four bilinear weights times
+// dlambda/(2 pi) c_n / v* fbar(x) into the view's box held in LDS (LDS float64 atomics); the
+// box of the previous view is flushed meanwhile from the other buffer to g^F-bar with one
+// global float atomic per non-zero detector cell (cells of the zero padding are dropped,
+// as the forward reads zeros there), and left zeroed for its next use.
+// ---------------------------------------------------------------------------------
+// The adjoint's LDS boxes accumulate in float64: the hardware's LDS float64 atomic add is
+// several times faster here than its float32 one, and exact enough that the flushed float32
+// sums round once.  Group words are bytes while the groups fit in 4 bits, so that the
+// double-buffered boxes still leave room for four workgroups per CU.
+constexpr int kLPT = kLP;
+constexpr int kHullT = 2000;
+
+template <int KZ>
+struct BpTShared {
+    static constexpr int NG = KZ / kKG;
+    using Word = typename std::conditional<(NG <= 4), unsigned char, unsigned short>::type;
+    static constexpr int kFull = NG <= 4 ? 4 : 8;
+    __attribute__((aligned(16))) double box[2][kLPT * lds_rows<KZ>()];
+    Word words[4][kHullT];
+    int red[8];
+};
+
+template <int KZ, bool P4>
+__device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *__restrict__ gFbar,
+                         int rows, int cols, long long first_view,
+                         const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
+                         int bxi, int byi, int bz, BpTShared<KZ> &S) {
+    static_assert(KZ % kKG == 0 && KZ / kKG <= 8, "groups use 8-bit masks");
+    constexpr int kLR = lds_rows<KZ>();
+    constexpr int NG = KZ / kKG;
+    auto &box = S.box;
+    auto &words = S.words;
+    auto &red = S.red;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int ix = bxi * kT + (tid & (kT - 1));
+    const int iy = byi * kT + (tid >> 4);
+    const int pitch = bz / p.runs;
+    const int run = bz % p.runs;
+    const int j0 = run * KZ;
+    const int slices = min(p.ns, p.nz - pitch * p.ns);
+    const int nrun = min(KZ, slices - j0);
+    if (nrun <= 0) return;                                   // uniform over the workgroup
+    const bool inxy = ix < p.nx && iy < p.ny;
+    const long long base = (long long)p.n_lo + (long long)pitch * p.Nv;   // view of m = 0
+    const int iz0 = pitch * p.ns + j0;
+
+    float A[KZ], B[KZ], fb[KZ];
+    int wlo = INT_MAX, whi = INT_MIN;
+    int g_alo[NG], g_ahi[NG], g_flo[NG], g_fhi[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        int alo = INT_MAX, ahi = INT_MIN, flo = INT_MIN, fhi = INT_MAX;
+#pragma unroll
+        for (int s = 0; s < kKG; ++s) {
+            const int jj = g * kKG + s;
+            A[jj] = 3.0e38f;
+            B[jj] = -3.0e38f;
+            fb[jj] = 0.0f;
+            if (inxy && jj < nrun) {
+                const PiEntry e = ldg(p.pi + ((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix);
+                const long long nf = base + e.nf, nl = base + e.nl;
+                if (e.nf <= e.nl && nf - 1 >= 0 && nl + 1 <= p.n_views - 1) {
+                    A[jj] = e.li - 0.5f;
+                    B[jj] = e.lo + 0.5f;
+                    fb[jj] = ldg(fvol + ((size_t)(iz0 + jj) * p.ny + iy) * p.nx + ix) * p.scale;
+                    alo = min(alo, e.nf);
+                    ahi = max(ahi, e.nl);
+                    flo = max(flo, (int)ceilf(A[jj] + 1.0f) + 1);
+                    fhi = min(fhi, (int)floorf(B[jj] - 1.0f) - 1);
+                }
+            }
+        }
+        g_alo[g] = wave_min(alo);
+        g_ahi[g] = wave_max(ahi);
+        g_flo[g] = wave_max(flo);
+        g_fhi[g] = wave_min(fhi);
+        wlo = min(wlo, g_alo[g]);
+        whi = max(whi, g_ahi[g]);
+    }
+    if (lane == 0) {
+        red[wave] = wlo;
+        red[4 + wave] = whi;
+    }
+    // both box buffers start zeroed (every flush leaves its cells zero again)
+    for (int i = tid; i < 2 * kLPT * kLR; i += kNT) (&box[0][0])[i] = 0.0;
+    __syncthreads();
+    const int mlo = __builtin_amdgcn_readfirstlane(min(min(red[0], red[1]), min(red[2], red[3])));
+    const int mhi = __builtin_amdgcn_readfirstlane(max(max(red[4], red[5]), max(red[6], red[7])));
+    using Word = typename BpTShared<KZ>::Word;
+    constexpr int kFull = BpTShared<KZ>::kFull;
+    const bool use_words = mhi - mlo + 1 <= kHullT;
+    if (use_words) {
+        for (int w = lane; w <= mhi - mlo; w += 64) {
+            const int m = mlo + w;
+            unsigned word = 0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (m >= g_alo[g] && m <= g_ahi[g]) word |= 1u << g;
+                if (m >= g_flo[g] && m <= g_fhi[g]) word |= 1u << (kFull + g);
+            }
+            words[wave][w] = (Word)word;
+        }
+    }
+    __syncthreads();
+
+    const float x = fmaf((float)ix, p.dx, p.x_first);
+    const float y = fmaf((float)iy, p.dy, p.y_first);
+    const float zoff = (float)j0 * p.dz;
+    const uint2 *__restrict__ boxes =
+        box_tab + ((size_t)(run * p.tiles_y + byi) * p.tiles_x + bxi) * p.W;
+    const size_t vstride = (size_t)rows * cols;
+    // flush of view m's box from buffer buf: lanes over 4 rows x 64 columns per pass
+    auto flush = [&](int m, const BpBox &b, int buf) {
+        double *bx = box[buf];
+        float *img = gFbar + (size_t)(base + m - first_view) * vstride;
+        const int cc = tid & 63;
+        for (int rr = tid >> 6; rr < b.nr; rr += 4) {
+            double *cell = bx + rr * kLPT + cc;
+            const double v = *cell;
+            if (v != 0.0) {
+                *cell = 0.0;
+                const int r = b.r0 + rr, c = b.c0 + cc;
+                if ((unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols)
+                    atomicAdd(img + (size_t)r * cols + c, (float)v);
+            }
+        }
+    };
+    BpBox prev_b = unpack_box(ldg(boxes + (mlo <= mhi ? mlo : 0)));
+    for (int m = mlo; m <= mhi; ++m) {
+        const int buf = (m - mlo) & 1;
+        const BpBox b = unpack_box(ldg(boxes + m));
+        const float4 vt = ldg(view_tab + m);
+        const float u = fmaf(-x, vt.y, y * vt.x);
+        const float v = p.R - fmaf(x, vt.x, y * vt.y);
+        const float vinv = __builtin_amdgcn_rcpf(v);
+        const float rinv = __builtin_amdgcn_rsqf(fmaf(u, u, v * v));
+        float acol;
+        if (P4 || p.atan_deg >= 0) {
+            const float t = u * vinv;
+            const float s2 = t * t;
+            constexpr int deg = P4 ? 4 : 8;
+            float qa = p.atan_coef[deg];
+#pragma unroll
+            for (int k = deg - 1; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
+            acol = t * qa;
+        } else {
+            acol = atan2f(u, v) * p.inv_dalpha;
+        }
+        const float cc = med3(acol + (p.col_c - (float)b.c0), 0.0f, (float)(b.nc - 2));
+        const int c0 = (int)cc;
+        const float tc = cc - (float)c0;
+        const float q = p.q_scale * rinv;
+        const float rb = fmaf(q, vt.z + zoff, p.row_c - (float)b.r0);
+        const float st = q * p.dz;
+        const float rmax = (float)(b.nr - 2);
+        const float mf = (float)m;
+        unsigned word = (1u << NG) - 1u;
+        if (use_words) word = __builtin_amdgcn_readfirstlane(words[wave][m - mlo]);
+        double *bx = box[buf] + c0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (!(word & (1u << g))) continue;
+            const bool full = word & (1u << (kFull + g));
+#pragma unroll
+            for (int s = 0; s < kKG; ++s) {
+                const int jj = g * kKG + s;
+                float a = vinv * fb[jj];
+                if (!full) a *= med3(fminf(mf - A[jj], B[jj] - mf), 0.0f, 1.0f);
+                if (a != 0.0f) {
+                    const float rr = med3(fmaf((float)jj, st, rb), 0.0f, rmax);
+                    const int r0 = (int)rr;
+                    const float tr = __builtin_amdgcn_fractf(rr);
+                    const float a1 = a * tr, a0 = a - a1;          // rows r0, r0 + 1
+                    const float a01 = a0 * tc, a11 = a1 * tc;        // column c0 + 1
+                    double *cell = bx + r0 * kLPT;
+                    atomicAdd(cell, (double)(a0 - a01));
+                    atomicAdd(cell + 1, (double)a01);
+                    atomicAdd(cell + kLPT, (double)(a1 - a11));
+                    atomicAdd(cell + kLPT + 1, (double)a11);
+                }
+            }
+        }
+        if (m > mlo) flush(m - 1, prev_b, buf ^ 1);
+        prev_b = b;
+        __syncthreads();
+    }
+    if (mlo <= mhi) flush(mhi, prev_b, (mhi - mlo) & 1);
+}
+
+template <int KZ, bool P4>
+__global__ __launch_bounds__(kNT) void k_bpT_lds(BpArgs p, const float *__restrict__ fvol,
+                                                 float *__restrict__ gFbar, int rows, int cols,
+                                                 long long first_view,
+                                                 const float4 *__restrict__ view_tab,
+                                                 const uint2 *__restrict__ box_tab) {
+    __shared__ BpTShared<KZ> S;
+    bpT_tile<KZ, P4>(p, fvol, gFbar, rows, cols, first_view, view_tab, box_tab, blockIdx.x,
+                     blockIdx.y, blockIdx.z, S);
+}
+
+// ---------------------------------------------------------------------------------
+// Adjoint of the backprojection (the transpose of the operator above, acting on an
+// unpadded g^F cotangent).
+// ---------------------------------------------------------------------------------
+constexpr int kTile = 8;          // 8 x 8 lanes per wave
+constexpr int kKZ = 8;            // slices per lane
+
+// Transpose: gFbar[n] += dlambda/(2 pi) c_n / v*_n * fbar(x) spread over the four bilinear
+// taps (global float atomics; the adjoint's only non-deterministic summation order).
+template <int KZ>
+__global__ __launch_bounds__(64) void k_backproject_T(KParams p, const float *__restrict__ gvol,
+                                                      float *__restrict__ gFbar, int runs_per_pitch) {
+    const int lane = threadIdx.x;
+    const int ix = blockIdx.x * kTile + (lane & (kTile - 1));
+    const int iy = blockIdx.y * kTile + (lane >> 3);
+    const int pitch = blockIdx.z / runs_per_pitch;
+    const int j0 = (blockIdx.z % runs_per_pitch) * KZ;
+    const int slices = min(p.ns, p.nz - pitch * p.ns);
+    const int nrun = min(KZ, slices - j0);
+    if (nrun <= 0) return;
+    const bool inxy = ix < p.nx && iy < p.ny;
+    const long long base = (long long)p.n_lo + (long long)pitch * p.Nv;
+    float A[KZ], B[KZ], g[KZ];
+    int mlo = INT_MAX, mhi = INT_MIN;
+    const int iz0 = pitch * p.ns + j0;
+#pragma unroll
+    for (int jj = 0; jj < KZ; ++jj) {
+        A[jj] = 3.0e38f;
+        B[jj] = -3.0e38f;
+        g[jj] = 0.0f;
+        if (inxy && jj < nrun) {
+            const PiEntry e = p.pi[((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix];
+            const long long nf = base + e.nf, nl = base + e.nl;
+            if (e.nf <= e.nl && nf - 1 >= 0 && nl + 1 <= p.n_views - 1) {
+                A[jj] = e.li - 0.5f;
+                B[jj] = e.lo + 0.5f;
+                g[jj] = gvol[((size_t)(iz0 + jj) * p.ny + iy) * p.nx + ix] * p.scale;
+                mlo = min(mlo, e.nf);
+                mhi = max(mhi, e.nl);
+            }
+        }
+    }
+    mlo = __builtin_amdgcn_readfirstlane(wave_min(mlo));
+    mhi = __builtin_amdgcn_readfirstlane(wave_max(mhi));
+    const float x = fmaf((float)ix, p.dx, p.x_first);
+    const float y = fmaf((float)iy, p.dy, p.y_first);
+    const float zoff = (float)j0 * p.dz;
+    const size_t rc = (size_t)p.rows * p.cols;
+    for (int m = mlo; m <= mhi; ++m) {
+        const float4 vt = p.view[m];
+        const float u = fmaf(-x, vt.y, y * vt.x);
+        const float v = p.R - fmaf(x, vt.x, y * vt.y);
+        const float vinv = 1.0f / v;
+        const float rinv = rsqrtf(fmaf(u, u, v * v));
+        const float cc = fmaf(atan2f(u, v), p.inv_dalpha, p.col_c);
+        const float ccl = fminf(fmaxf(cc, -2.0f), (float)p.cols);
+        const float c0f = floorf(ccl);
+        const float tc = ccl - c0f;
+        const int c0 = (int)c0f;
+        const float q = p.D * rinv * p.inv_dw;
+        const float ez = vt.z + zoff;
+        float *img = gFbar + (size_t)(base + m - p.first_view) * rc;
+        const float mf = (float)m;
+#pragma unroll
+        for (int jj = 0; jj < KZ; ++jj) {
+            const float cw = fminf(fmaxf(fminf(mf - A[jj], B[jj] - mf), 0.0f), 1.0f);
+            const float amp = cw * vinv * g[jj];
+            if (amp == 0.0f) continue;
+            const float rr = fmaf(q, fmaf((float)jj, p.dz, ez), p.row_c);
+            const float rrl = fminf(fmaxf(rr, -2.0f), (float)p.rows);
+            const float r0f = floorf(rrl);
+            const float tr = rrl - r0f;
+            const int r0 = (int)r0f;
+            const float w00 = (1.0f - tr) * (1.0f - tc), w01 = (1.0f - tr) * tc;
+            const float w10 = tr * (1.0f - tc), w11 = tr * tc;
+            if ((unsigned)r0 < (unsigned)p.rows) {
+                if ((unsigned)c0 < (unsigned)p.cols) atomicAdd(img + r0 * p.cols + c0, amp * w00);
+                if ((unsigned)(c0 + 1) < (unsigned)p.cols) atomicAdd(img + r0 * p.cols + c0 + 1, amp * w01);
+            }
+            if ((unsigned)(r0 + 1) < (unsigned)p.rows) {
+                if ((unsigned)c0 < (unsigned)p.cols) atomicAdd(img + (r0 + 1) * p.cols + c0, amp * w10);
+                if ((unsigned)(c0 + 1) < (unsigned)p.cols)
+                    atomicAdd(img + (r0 + 1) * p.cols + c0 + 1, amp * w11);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFbar, hipStream_t s) {
+    if (k.bp_all_fit) {
+        // tiled adjoint: LDS-accumulated boxes, one global atomic per cell and view
+        const dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
+        const BpArgs a = bp_args(k);
+        const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
+        const bool p4 = k.atan_deg >= 0 && k.atan_deg <= 4;
+#define KATS_BPT(KZ, P4) hipLaunchKernelGGL((k_bpT_lds<KZ, P4>), grid, dim3(kNT), 0, s, a, gvol, gFbar, \
+                                            k.rows, k.cols, k.first_view, k.view, boxes)
+        switch (k.bp_kz) {
+            case 8: if (p4) KATS_BPT(8, true); else KATS_BPT(8, false); break;
+            case 32: if (p4) KATS_BPT(32, true); else KATS_BPT(32, false); break;
+            default: if (p4) KATS_BPT(16, true); else KATS_BPT(16, false); break;
+        }
+#undef KATS_BPT
+        return hipGetLastError();
+    }
+    // plans with boxes beyond the LDS tile: per-tap global atomics
+    const int ns_eff = k.ns < k.nz ? k.ns : k.nz;
+    const int runs = (ns_eff + kKZ - 1) / kKZ;
+    dim3 grid((k.nx + kTile - 1) / kTile, (k.ny + kTile - 1) / kTile, (unsigned)(k.n_pitches * runs));
+    hipLaunchKernelGGL(k_backproject_T<kKZ>, grid, dim3(64), 0, s, k, gvol, gFbar, runs);
+    return hipGetLastError();
+}
+
+
+}  // namespace kats
