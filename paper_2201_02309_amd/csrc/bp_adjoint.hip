@@ -60,7 +60,10 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     const long long base = (long long)p.n_lo + (long long)pitch * p.Nv;   // view of m = 0
     const int iz0 = pitch * p.ns + j0;
 
-    float A[KZ], B[KZ], fb[KZ];
+    // register r of a lane holds slice (r + off) mod KZ: lanes of a wave that lie on one ray
+    // then scatter slices of different z (different detector rows) in the same instruction
+    const int off = ((tid & 15) + 4 * ((tid >> 4) & 3)) & (KZ - 1);
+    float A[KZ], B[KZ], fb[KZ], sf[KZ];
     int wlo = INT_MAX, whi = INT_MIN;
     int g_alo[NG], g_ahi[NG], g_flo[NG], g_fhi[NG];
 #pragma unroll
@@ -68,21 +71,23 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         int alo = INT_MAX, ahi = INT_MIN, flo = INT_MIN, fhi = INT_MAX;
 #pragma unroll
         for (int s = 0; s < kKG; ++s) {
-            const int jj = g * kKG + s;
-            A[jj] = 3.0e38f;
-            B[jj] = -3.0e38f;
-            fb[jj] = 0.0f;
+            const int r = g * kKG + s;                      // register
+            const int jj = (r + off) & (KZ - 1);            // slice
+            sf[r] = (float)jj;
+            A[r] = 3.0e38f;
+            B[r] = -3.0e38f;
+            fb[r] = 0.0f;
             if (inxy && jj < nrun) {
                 const PiEntry e = ldg(p.pi + ((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix);
                 const long long nf = base + e.nf, nl = base + e.nl;
                 if (e.nf <= e.nl && nf - 1 >= 0 && nl + 1 <= p.n_views - 1) {
-                    A[jj] = e.li - 0.5f;
-                    B[jj] = e.lo + 0.5f;
-                    fb[jj] = ldg(fvol + ((size_t)(iz0 + jj) * p.ny + iy) * p.nx + ix) * p.scale;
+                    A[r] = e.li - 0.5f;
+                    B[r] = e.lo + 0.5f;
+                    fb[r] = ldg(fvol + ((size_t)(iz0 + jj) * p.ny + iy) * p.nx + ix) * p.scale;
                     alo = min(alo, e.nf);
                     ahi = max(ahi, e.nl);
-                    flo = max(flo, (int)ceilf(A[jj] + 1.0f) + 1);
-                    fhi = min(fhi, (int)floorf(B[jj] - 1.0f) - 1);
+                    flo = max(flo, (int)ceilf(A[r] + 1.0f) + 1);
+                    fhi = min(fhi, (int)floorf(B[r] - 1.0f) - 1);
                 }
             }
         }
@@ -179,11 +184,11 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
             const bool full = word & (1u << (kFull + g));
 #pragma unroll
             for (int s = 0; s < kKG; ++s) {
-                const int jj = g * kKG + s;
-                float a = vinv * fb[jj];
-                if (!full) a *= med3(fminf(mf - A[jj], B[jj] - mf), 0.0f, 1.0f);
+                const int r = g * kKG + s;                  // register (slice sf[r])
+                float a = vinv * fb[r];
+                if (!full) a *= med3(fminf(mf - A[r], B[r] - mf), 0.0f, 1.0f);
                 if (a != 0.0f) {
-                    const float rr = med3(fmaf((float)jj, st, rb), 0.0f, rmax);
+                    const float rr = med3(fmaf(sf[r], st, rb), 0.0f, rmax);
                     const int r0 = (int)rr;
                     const float tr = __builtin_amdgcn_fractf(rr);
                     const float a1 = a * tr, a0 = a - a1;          // rows r0, r0 + 1
