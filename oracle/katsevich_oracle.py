@@ -31,6 +31,12 @@ each, listed with reasons in the design notes):
   (radius R sin(min(-alpha_first, alpha_last))) and every view with c_n > 0, together
   with both derivative neighbours, was acquired; otherwise its value is 0.
 
+Option (half=True): the derivative of eq. Deriv at the centre of each 2 x 2 cell of
+(lambda, alpha) samples, every partial derivative the mean of the two forward differences
+across the cell.  The filtered data then live on the grid lambda_{n+1/2}, alpha_{c+1/2}
+(half_sample_geometry), on which every later step runs unchanged; the validity rule keeps
+its one-view margin in that grid.
+
 All arithmetic is float64 and round-to-nearest.  Integer tables are floor() of float64
 values.
 """
@@ -98,6 +104,29 @@ def derivative_lw(scan: Scan, g) -> np.ndarray:
     lw = scan.D / np.sqrt(scan.D ** 2 + scan.w ** 2)
     out[1:-1] = lw[None, :, None] * (d_lam + d_alpha)
     return out
+
+
+def half_sample_geometry(geom: dict) -> dict:
+    """Grid of the filtered data under the half-sample derivative: views at lambda_{n+1/2}
+    (n = 0 .. N-2) and columns at alpha_{c+1/2} (c = 0 .. cols-2).  Columns are centred on
+    the detector, so one column fewer at the same offset puts them half a column on."""
+    h = dict(geom)
+    h["lambda_first"] = float(geom.get("lambda_first", 0.0)) + math.pi / int(geom["views_per_turn"])
+    h["det_cols"] = int(geom["det_cols"]) - 1
+    h["n_views"] = int(geom["n_views"]) - 1
+    return h
+
+
+def derivative_lw_half(scan_h: Scan, g) -> np.ndarray:
+    """Eqs. Deriv and LW at the cell centres (lambda_{n+1/2}, alpha_{c+1/2}): each partial
+    derivative is the mean of the two forward differences across the 2 x 2 cell of native
+    samples (n, n+1) x (c, c+1).  g: native views [V, rows, cols] -> [V-1, rows, cols-1];
+    scan_h is the Scan of half_sample_geometry."""
+    g = np.asarray(g, dtype=np.float64)
+    d_lam = (g[1:, :, :-1] - g[:-1, :, :-1] + g[1:, :, 1:] - g[:-1, :, 1:]) / (2.0 * scan_h.dlam)
+    d_alpha = (g[:-1, :, 1:] - g[:-1, :, :-1] + g[1:, :, 1:] - g[1:, :, :-1]) / (2.0 * scan_h.dalpha)
+    lw = scan_h.D / np.sqrt(scan_h.D ** 2 + scan_h.w ** 2)
+    return lw[None, :, None] * (d_lam + d_alpha)
 
 
 # ----------------------------------------------------------------------------------
@@ -245,10 +274,23 @@ class FilterTables:
 
 
 def filter_views(scan: Scan, g, tables: FilterTables | None = None, chunk=256,
-                 progress=None) -> np.ndarray:
-    """Steps 1-6 of Sec. II on a block of consecutive views -> g^F (first/last view 0)."""
+                 progress=None, half=False) -> np.ndarray:
+    """Steps 1-6 of Sec. II on a block of consecutive views -> g^F (first/last view 0).
+    half: scan is the half-sample grid and g the V+1 native views around its V views."""
     tables = tables or FilterTables(scan)
     g = np.asarray(g, dtype=np.float64)
+    if half:
+        V = g.shape[0] - 1
+        out = np.zeros((max(V, 0), scan.rows, scan.cols))
+        for a in range(0, V, chunk):
+            if progress is not None:
+                progress(a, V)
+            b = min(V, a + chunk)
+            g2 = derivative_lw_half(scan, g[a:b + 1])
+            g3 = forward_rebin(scan, g2, tables.fr)
+            g4 = hilbert(scan, g3, tables.T)
+            out[a:b] = backward_rebin_cos(scan, g4, tables.br)
+        return out
     V = g.shape[0]
     out = np.zeros((V, scan.rows, scan.cols))
     for a in range(1, V - 1, chunk):
@@ -427,8 +469,11 @@ def valid_mask(scan: Scan, nf, nl, fov):
     return fov & (nf - 1 >= 0) & (nl + 1 <= scan.N - 1)
 
 
-def recon(scan: Scan, grid: dict, g, mode="pitch", tables=None, ftables=None):
+def recon(scan: Scan, grid: dict, g, mode="pitch", tables=None, ftables=None, half=False):
     """Full reconstruction f[nz, ny, nx] and validity mask.
+
+    half: half-sample derivative; scan is the Scan of half_sample_geometry(native geometry)
+    and g the native sinogram [N + 1, rows, cols + 1].
 
     mode="pitch": the paper's scheme -- PI tables of the first pitch reused for every
     pitch k (lambda shifted by 2 pi k), each pitch filtering its own lambda-sliced
@@ -441,8 +486,9 @@ def recon(scan: Scan, grid: dict, g, mode="pitch", tables=None, ftables=None):
     valid = np.zeros((nz, ny, nx), dtype=bool)
     x, y = grid_xy(grid)
     ftables = ftables or FilterTables(scan)
+    ext = 1 if half else 0                  # native views beyond the last filtered one
     if mode == "whole":
-        gF = filter_views(scan, g, ftables)
+        gF = filter_views(scan, g, ftables, half=half)
         z = grid["z_first"] + np.arange(nz) * grid["dz"]
         Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
         lam_i, lam_o = pi_line(scan, X, Y, Z)
@@ -470,7 +516,7 @@ def recon(scan: Scan, grid: dict, g, mode="pitch", tables=None, ftables=None):
         valid[sl] = vk
         if not vk.any():
             continue
-        gF = filter_views(scan, g[a:b + 1], ftables)
+        gF = filter_views(scan, g[a:b + 1 + ext], ftables, half=half)
         for jj, (iz, j) in enumerate(zip(sl, js)):
             m = vk[jj]
             if not m.any():
@@ -517,20 +563,27 @@ def backproject_T(scan: Scan, fbar, n0, nviews, x, y, z, li, lo, nf, nl, lam_shi
     return out
 
 
-def filter_views_T(scan: Scan, gFbar, tables: FilterTables | None = None) -> np.ndarray:
-    """Transpose of filter_views() on a block of consecutive views."""
+def filter_views_T(scan: Scan, gFbar, tables: FilterTables | None = None,
+                   half=False) -> np.ndarray:
+    """Transpose of filter_views() on a block of consecutive views (half: returns the
+    V+1 native views [V+1, rows, cols+1])."""
     tables = tables or FilterTables(scan)
     gFbar = np.asarray(gFbar, np.float64)
     V = gFbar.shape[0]
-    gbar = np.zeros_like(gFbar)
-    if V < 3:
-        return gbar
+    if half:
+        gbar = np.zeros((V + 1, scan.rows, scan.cols + 1))
+        views = range(0, V)
+    else:
+        gbar = np.zeros_like(gFbar)
+        if V < 3:
+            return gbar
+        views = range(1, V - 1)
     k0, tb = tables.br
     r0, tf = tables.fr
     c_idx = np.arange(scan.cols)
     cosa = np.cos(scan.alpha)
     lw = scan.D / np.sqrt(scan.D ** 2 + scan.w ** 2)
-    for n in range(1, V - 1):
+    for n in views:
         gf = gFbar[n] * cosa[None, :]
         g4 = np.zeros((scan.n_psi, scan.cols))                 # BR^T (scatter)
         np.add.at(g4, (k0, np.broadcast_to(c_idx, k0.shape)), (1 - tb) * gf)
@@ -542,6 +595,13 @@ def filter_views_T(scan: Scan, gFbar, tables: FilterTables | None = None) -> np.
             ok = (r >= 0) & (r < scan.rows)
             np.add.at(g2, (r[ok], np.broadcast_to(c_idx, r.shape)[ok]), (wt * g3)[ok])
         g1 = lw[:, None] * g2                                   # LW^T
+        if half:                                                # half-sample Deriv^T
+            a, b = 1.0 / (2 * scan.dlam), 1.0 / (2 * scan.dalpha)
+            gbar[n, :, :-1] -= (a + b) * g1
+            gbar[n, :, 1:] += (b - a) * g1
+            gbar[n + 1, :, :-1] += (a - b) * g1
+            gbar[n + 1, :, 1:] += (a + b) * g1
+            continue
         gbar[n + 1] += g1 / (2 * scan.dlam)                     # Deriv^T (lambda)
         gbar[n - 1] -= g1 / (2 * scan.dlam)
         gbar[n, :, 1:] += g1[:, :-1] / (2 * scan.dalpha)        # Deriv^T (alpha)
@@ -549,12 +609,13 @@ def filter_views_T(scan: Scan, gFbar, tables: FilterTables | None = None) -> np.
     return gbar
 
 
-def recon_T(scan: Scan, grid: dict, fbar, tables=None, ftables=None) -> np.ndarray:
+def recon_T(scan: Scan, grid: dict, fbar, tables=None, ftables=None, half=False) -> np.ndarray:
     """Exact transpose of recon(mode="pitch"): volume cotangent -> sinogram cotangent.
-    Views shared by adjacent pitches accumulate."""
+    Views shared by adjacent pitches accumulate.  half: as in recon (native-shaped result)."""
     nx, ny = int(grid["nx"]), int(grid["ny"])
     fbar = np.asarray(fbar, np.float64)
-    gbar = np.zeros((scan.N, scan.rows, scan.cols))
+    ext = 1 if half else 0
+    gbar = np.zeros((scan.N + ext, scan.rows, scan.cols + ext))
     x, y = grid_xy(grid)
     ftables = ftables or FilterTables(scan)
     tab = tables or pitch_tables(scan, grid)
@@ -582,7 +643,7 @@ def recon_T(scan: Scan, grid: dict, fbar, tables=None, ftables=None) -> np.ndarr
                                    np.full(m.sum(), zj), tab["li"][j][m] + shift,
                                    tab["lo"][j][m] + shift, nf[jj][m], nl[jj][m],
                                    lam_shift=TWO_PI * k)
-        gbar[a:b + 1] += filter_views_T(scan, gFbar, ftables)
+        gbar[a:b + 1 + ext] += filter_views_T(scan, gFbar, ftables, half=half)
     return gbar
 
 

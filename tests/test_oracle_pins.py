@@ -427,3 +427,149 @@ def test_oracle_adjoint_dot_product():
     rhs = float(np.sum(g * gbar))
     assert valid.any()
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(f) * np.linalg.norm(fbar) * 10
+
+
+# ---------------------------------------------------------------- half-sample derivative option
+def test_half_sample_derivative_converges():
+    """The 2 x 2 cell stencil converges at second order to the exact derivative at constant
+    ray direction at the cell centre (lambda_{n+1/2}, alpha_{c+1/2}), obtained from the
+    closed-form line integral with the source moved along the helix."""
+    ph = {"kind": "gaussians", "centre": np.array([[10.0, -5.0, 30.0], [-20.0, 15.0, 25.0]]),
+          "sigma": np.array([12.0, 8.0]), "amp": np.array([1.0, 0.6])}
+    errs = []
+    for level in range(3):
+        nv = 360 * 2 ** level
+        cols = 64 * 2 ** level
+        wl = configs.make_workload("d", feed=40.0, cols=cols, rows=8, views_per_turn=nv,
+                                   turns=1, nxy=16, nz=4, dxy=4.0, slices_per_pitch=10,
+                                   r_cov=60.0)
+        geom = wl.geom.as_dict()
+        gh = O.half_sample_geometry(geom)
+        sh = O.Scan(gh)
+        n = nv // 4
+        g = phantom.project(ph, geom, views=[n, n + 1])
+        g1 = O.derivative_lw_half(sh, g)[0] / (sh.D / np.sqrt(sh.D ** 2 + sh.w ** 2))[:, None]
+        src, d = phantom.scan_rays(gh, [n])           # rays of the half-sample cell centres
+        lam = sh.lam(n)
+        eps = 1e-5
+
+        def src_at(l):
+            return np.array([sh.R * math.cos(l + sh.lambda0),
+                             sh.R * math.sin(l + sh.lambda0), sh.z0 + sh.h * l])
+        exact = (phantom.line_integrals(ph, src_at(lam + eps), d[0]) -
+                 phantom.line_integrals(ph, src_at(lam - eps), d[0])) / (2 * eps)
+        sl = slice(cols // 4, 3 * cols // 4)
+        errs.append(np.abs(g1[:, sl] - exact[:, sl]).max() / np.abs(exact[:, sl]).max())
+    print(errs)
+    assert errs[0] < 2e-2
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_half_sample_geometry_is_the_cell_centres():
+    geom = configs.tiny(cols=32, rows=6, views_per_turn=48, turns=3).geom.as_dict()
+    geom["col_offset"] = 0.25
+    s, sh = O.Scan(geom), O.Scan(O.half_sample_geometry(geom))
+    assert sh.cols == s.cols - 1 and sh.N == s.N - 1 and sh.rows == s.rows
+    assert np.allclose(sh.alpha, 0.5 * (s.alpha[:-1] + s.alpha[1:]), rtol=0, atol=1e-15)
+    assert np.allclose(sh.lam(np.arange(sh.N)), 0.5 * (s.lam(np.arange(s.N - 1)) +
+                                                       s.lam(np.arange(1, s.N))), atol=1e-13)
+    assert np.array_equal(sh.w, s.w)
+
+
+def test_half_sample_uniform_ball_reconstructs_positive_density():
+    """As the central-difference ball test; the averaged stencil smooths across columns, so
+    its error in alpha is larger at equal sampling (64 columns: 5 %, 128: 1.2 %, i.e. second
+    order), and the test uses 128 columns."""
+    wl = configs.tiny(nxy=24, nz=12, cols=128, rows=8, views_per_turn=90)
+    geom = wl.geom.as_dict()
+    sh = O.Scan(O.half_sample_geometry(geom))
+    gr = wl.grid.as_dict()
+    zc = gr["z_first"] + 0.5 * (gr["nz"] - 1) * gr["dz"]
+    ph = {"kind": "ellipsoids", "centre": np.array([[0, 0, zc]]), "axes": np.array([[15.0] * 3]),
+          "rot": np.array([np.eye(3)]), "density": np.array([1.0])}
+    g = phantom.project(ph, geom)
+    f, valid = O.recon(sh, gr, g, half=True)
+    c = gr["nz"] // 2
+    # (the half-sample grid has one column less, so the FOV loses the grid corners)
+    assert valid[c, 9:15, 9:15].all()
+    assert np.abs(f[c, 9:15, 9:15] - 1.0).max() < 0.02
+
+
+def test_half_sample_recon_converges_with_central():
+    """Both derivative stencils discretise the same formula: on a smooth phantom inside the
+    fan, each reconstruction converges to the phantom at second order (error / 4 when the
+    view, column and row steps halve) and their difference shrinks with it."""
+    errs = []
+    for cols, rows, vpt in ((64, 8, 120), (128, 16, 240)):
+        ph = {"kind": "gaussians", "centre": np.array([[4.0, -3.0, 0.0], [-6.0, 5.0, 0.0]]),
+              "sigma": np.array([6.0, 4.0]), "amp": np.array([1.0, 0.5])}
+        wl = configs.make_workload("h", feed=24.0, cols=cols, rows=rows, views_per_turn=vpt,
+                                   turns=3, nxy=16, nz=6, dxy=2.0, slices_per_pitch=12,
+                                   r_cov=50.0)
+        geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+        ph["centre"][:, 2] = gr["z_first"] + 0.5 * (gr["nz"] - 1) * gr["dz"]
+        g = phantom.project(ph, geom)
+        f0, v0 = O.recon(O.Scan(geom), gr, g)
+        f1, v1 = O.recon(O.Scan(O.half_sample_geometry(geom)), gr, g, half=True)
+        m = v0 & v1
+        assert m.sum() > 1000
+        P = np.stack(np.meshgrid(gr["z_first"] + np.arange(gr["nz"]) * gr["dz"],
+                                 gr["y_first"] + np.arange(gr["ny"]) * gr["dy"],
+                                 gr["x_first"] + np.arange(gr["nx"]) * gr["dx"],
+                                 indexing="ij")[::-1], -1)
+        truth = phantom.density(ph, P)
+        nrm = np.linalg.norm(truth[m])
+        errs.append((np.linalg.norm((f0 - truth)[m]) / nrm, np.linalg.norm((f1 - truth)[m]) / nrm,
+                     np.linalg.norm((f1 - f0)[m]) / nrm))
+    print(errs)
+    (c0, h0, d0), (c1, h1, d1) = errs
+    assert c0 < 0.05 and h0 < 0.05 and d0 < 0.03
+    assert c0 / c1 > 3.0 and h0 / h1 > 3.0 and d0 / d1 > 3.0
+
+
+def test_oracle_adjoint_dot_product_half_sample():
+    wl = configs.tiny(nxy=12, nz=12, cols=32, rows=6, views_per_turn=48, turns=3, feed=24.0,
+                      dxy=3.0, slices_per_pitch=8)
+    geom = wl.geom.as_dict()
+    sh = O.Scan(O.half_sample_geometry(geom))
+    gr = wl.grid.as_dict()
+    rng = np.random.default_rng(11)
+    g = rng.normal(size=(geom["n_views"], geom["det_rows"], geom["det_cols"]))
+    fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"]))
+    tab = O.pitch_tables(sh, gr)
+    f, valid = O.recon(sh, gr, g, tables=tab, half=True)
+    gbar = O.recon_T(sh, gr, fbar, tables=tab, half=True)
+    assert gbar.shape == g.shape and valid.any()
+    lhs, rhs = float(np.sum(f * fbar)), float(np.sum(g * gbar))
+    assert abs(lhs - rhs) <= 1e-11 * np.linalg.norm(f) * np.linalg.norm(fbar)
+
+
+# ---------------------------------------------------------------- detector offsets
+def test_shifted_detector_reconstructs_the_same_object():
+    """A detector whose centre is moved by (2.5 columns, 1.5 rows) and widened to cover the
+    same fan and Tam-Danielsson window sees the same rays at other indices; its
+    reconstruction stays that of the phantom.  Read with the offsets' signs flipped, the
+    same data give an error near 100 %."""
+    ph = {"kind": "gaussians", "centre": np.array([[4.0, -3.0, 0.0], [-6.0, 5.0, 0.0]]),
+          "sigma": np.array([6.0, 4.0]), "amp": np.array([1.0, 0.5])}
+    wl = configs.make_workload("h", feed=24.0, cols=64, rows=8, views_per_turn=120, turns=3,
+                               nxy=16, nz=6, dxy=2.0, slices_per_pitch=12, r_cov=50.0)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    ph["centre"][:, 2] = gr["z_first"] + 0.5 * (gr["nz"] - 1) * gr["dz"]
+    shifted = dict(geom, det_cols=geom["det_cols"] + 6, col_offset=2.5,
+                   det_rows=geom["det_rows"] + 4, row_offset=1.5)
+    g1 = phantom.project(ph, shifted)
+    f0, v0 = O.recon(O.Scan(geom), gr, phantom.project(ph, geom))
+    f1, v1 = O.recon(O.Scan(shifted), gr, g1)
+    f2, v2 = O.recon(O.Scan(dict(shifted, col_offset=-2.5, row_offset=-1.5)), gr, g1)
+    m = v0 & v1 & v2
+    P = np.stack(np.meshgrid(gr["z_first"] + np.arange(gr["nz"]) * gr["dz"],
+                             gr["y_first"] + np.arange(gr["ny"]) * gr["dy"],
+                             gr["x_first"] + np.arange(gr["nx"]) * gr["dx"], indexing="ij")[::-1], -1)
+    truth = phantom.density(ph, P)
+    nrm = np.linalg.norm(truth[m])
+    e1 = np.linalg.norm((f1 - truth)[m]) / nrm
+    d = np.linalg.norm((f1 - f0)[m]) / nrm
+    e2 = np.linalg.norm((f2 - truth)[m]) / nrm
+    print(e1, d, e2)
+    assert m.sum() > 1000 and e1 < 0.05 and d < 0.01 and e2 > 0.5
