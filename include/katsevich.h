@@ -81,11 +81,20 @@ typedef struct katsevich_grid {
 /* Plan options.  n_psi: number of kappa-lines sampled uniformly on
  * [-pi/2-alpha_m, pi/2+alpha_m] (eq. FR range; 0 -> 2*det_rows+1; must be >= 3);
  * n_threads: host threads used to build the plan (0 -> all hardware threads);
- * flags: reserved, 0; bp_slices: slices per backprojection register run (0 -> 16, else 8,
- * 16 or 32; a performance knob, results agree to rounding). */
+ * flags: 0 or KATS_FLAG_HALF_SAMPLE_DERIVATIVE (other bits are rejected);
+ * bp_slices: slices per backprojection register run (0 -> 16, else 8, 16 or 32; a
+ * performance knob, results agree to rounding). */
 typedef struct katsevich_options {
     int32_t n_psi, n_threads, flags, bp_slices;
 } katsevich_options;
+
+/* Derivative at constant direction (eq. Deriv) taken at the centre of every 2 x 2 cell of
+ * (lambda, alpha) samples instead of by central differences at the samples: each partial
+ * derivative is the mean of the two forward differences across the cell.  The filtered
+ * data then live on the cell centres, views at lambda_{n+1/2} (n < n_views-1) and columns
+ * at alpha_{c+1/2} (c < det_cols-1), and every later step runs on that grid; the sinogram
+ * and volume buffers keep their shapes.  Needs n_views >= 4 and det_cols >= 3. */
+#define KATS_FLAG_HALF_SAMPLE_DERIVATIVE 1
 
 typedef struct katsevich_plan_s *katsevich_plan_t;
 
@@ -109,7 +118,10 @@ typedef struct katsevich_plan_info {
     int32_t bp_box_rows, bp_box_cols;  /* largest detector footprint box of a backprojection
                                           tile; boxes up to 32 x 64 are staged in LDS, a plan
                                           with larger ones uses the kernel with an HBM path */
-    int32_t reserved;
+    int32_t half_sample;               /* 1 with KATS_FLAG_HALF_SAMPLE_DERIVATIVE: first_view,
+                                          last_view, window_lo and the g^F views then count
+                                          the cell-centre views lambda_{n+1/2}, and g^F has
+                                          det_cols-1 columns */
 } katsevich_plan_info;
 
 /* Table ids for katsevich_plan_export (host copies, for tests). */

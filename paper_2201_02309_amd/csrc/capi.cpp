@@ -72,6 +72,9 @@ KParams make_params(const PlanHost &P) {
     k.W = P.W;
     k.n_pitches = P.n_pitches;
     k.n_views = g.n_views;
+    k.half = P.half ? 1 : 0;
+    k.sino_cols = P.sino_cols;
+    k.sino_views = P.sino_views;
     k.first_view = P.first_view;
     k.n_filt = P.last_view >= P.first_view ? P.last_view - P.first_view + 1 : 0;
     const unsigned char *base = static_cast<const unsigned char *>(P.d_tables);
@@ -213,6 +216,7 @@ int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
     i.bp_slices = P.bp_kz;
     i.bp_box_rows = P.bp_box_rows;
     i.bp_box_cols = P.bp_box_cols;
+    i.half_sample = P.half ? 1 : 0;
     *out = i;
     return KATS_OK;
 }

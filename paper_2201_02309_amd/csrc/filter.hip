@@ -48,6 +48,33 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_lw(KParams p, const floa
     }
 }
 
+// Half-sample derivative: filtered view i (cell-centre view n = first_view + i, between
+// sinogram views n and n+1) and column c (between sinogram columns c and c+1).  Each partial
+// derivative is the mean of the two forward differences across the 2 x 2 cell; the thread
+// walks a run of views keeping the previous sinogram view's two samples in registers.
+__global__ __launch_bounds__(kElemThreads) void k_deriv_lw_half(KParams p, const float *__restrict__ sino,
+                                                                float *__restrict__ g2) {
+    const int c = blockIdx.x * kElemThreads + threadIdx.x;
+    const int r = blockIdx.y;
+    const long long i0 = (long long)blockIdx.z * kDerivRun;
+    if (c >= p.cols) return;
+    const long long i1 = i0 + kDerivRun < p.n_filt ? i0 + kDerivRun : p.n_filt;
+    const size_t src = (size_t)p.rows * p.sino_cols;          // sinogram view stride
+    const size_t rc = (size_t)p.rows * p.cols;
+    const float *col = sino + (size_t)r * p.sino_cols + c;    // sinogram (view 0, r, c)
+    const float w = p.lw[r];
+    long long n = p.first_view + i0;                          // 0 <= n, n+1 <= sino_views-1
+    float a0 = col[(size_t)n * src], a1 = col[(size_t)n * src + 1];
+    for (long long i = i0; i < i1; ++i, ++n) {
+        const float b0 = col[(size_t)(n + 1) * src], b1 = col[(size_t)(n + 1) * src + 1];
+        const float dl = ((b0 - a0) + (b1 - a1)) * p.inv_2dlam;
+        const float da = ((a1 - a0) + (b1 - b0)) * p.inv_2dalpha;
+        g2[(size_t)i * rc + (size_t)r * p.cols + c] = w * (dl + da);
+        a0 = b0;
+        a1 = b1;
+    }
+}
+
 __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -424,6 +451,26 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_T(KParams p, const float
     gsino[(size_t)n * rc + (size_t)r * p.cols + c] = vl + va;
 }
 
+// Transpose of the half-sample derivative (LW^T is applied by k_fr_lw_T): sinogram
+// sample (n, r, c) belongs to the cells (n-1 .. n) x (c-1 .. c) of the filtered grid.
+__global__ __launch_bounds__(kElemThreads) void k_deriv_T_half(KParams p, const float *__restrict__ g2bar,
+                                                               float *__restrict__ gsino) {
+    const long long n = blockIdx.x;                 // every sinogram view
+    const int r = blockIdx.y;
+    const int c = blockIdx.z * kElemThreads + threadIdx.x;
+    if (c >= p.sino_cols) return;
+    const size_t rc = (size_t)p.rows * p.cols;
+    auto at = [&](long long view, int col) -> float {
+        const long long i = view - p.first_view;
+        if (i < 0 || i >= p.n_filt || col < 0 || col >= p.cols) return 0.0f;
+        return g2bar[(size_t)i * rc + (size_t)r * p.cols + col];
+    };
+    const float a = p.inv_2dlam, b = p.inv_2dalpha;
+    const float v = (b - a) * at(n, c - 1) - (a + b) * at(n, c) + (a + b) * at(n - 1, c - 1) +
+                    (a - b) * at(n - 1, c);
+    gsino[((size_t)n * p.rows + r) * p.sino_cols + c] = v;
+}
+
 }  // namespace
 
 hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,
@@ -431,7 +478,10 @@ hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *
     if (k.n_filt <= 0) return hipSuccess;
     const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
     const unsigned runs = (unsigned)((k.n_filt + kDerivRun - 1) / kDerivRun);
-    hipLaunchKernelGGL(k_deriv_lw, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
+    if (k.half)
+        hipLaunchKernelGGL(k_deriv_lw_half, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
+    else
+        hipLaunchKernelGGL(k_deriv_lw, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
     launch_hilbert<false>(k, g2, g4, s);
     const int cbp = (k.gf_cols + kElemThreads - 1) / kElemThreads;
     hipLaunchKernelGGL(k_br_cos, dim3(cbp, (unsigned)k.n_filt), dim3(kElemThreads), 0, s, k, g4, gF);
@@ -448,8 +498,14 @@ hipError_t launch_filter_T(const KParams &k, const float *gFbar, float *g4bar, f
         hipLaunchKernelGGL(k_fr_lw_T, dim3((unsigned)k.n_filt, cb), dim3(kElemThreads), 0, s, k,
                            g4bar, g2bar);
     }
-    hipLaunchKernelGGL(k_deriv_T, dim3((unsigned)k.n_views, k.rows, cb), dim3(kElemThreads), 0, s,
-                       k, g2bar, gsino);
+    if (k.half) {
+        const int cbs = (k.sino_cols + kElemThreads - 1) / kElemThreads;
+        hipLaunchKernelGGL(k_deriv_T_half, dim3((unsigned)k.sino_views, k.rows, cbs), dim3(kElemThreads),
+                           0, s, k, g2bar, gsino);
+    } else {
+        hipLaunchKernelGGL(k_deriv_T, dim3((unsigned)k.n_views, k.rows, cb), dim3(kElemThreads), 0, s,
+                           k, g2bar, gsino);
+    }
     return hipGetLastError();
 }
 

@@ -23,6 +23,11 @@ struct KParams {
     int rows, cols, n_psi, fft_len, log2n;
     int Nv, n_lo, W, n_pitches;
     long long n_views, first_view, n_filt;
+    // sinogram as acquired: with the half-sample derivative (half = 1) views and columns of
+    // the filtered grid sit between those of the sinogram (sino_views = n_views + 1,
+    // sino_cols = cols + 1); otherwise the two grids coincide
+    int half, sino_cols;
+    long long sino_views;
     // device tables (inside the caller's bound table buffer)
     const float4 *view;
     const FrEntry *fr;

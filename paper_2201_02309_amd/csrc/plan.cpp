@@ -281,14 +281,32 @@ uint64_t pi_scratch_bytes(const katsevich_geometry &g, const katsevich_grid &gr)
     return 2 * align256(nvox * sizeof(double));
 }
 
-int build_plan(const katsevich_geometry &g, const katsevich_grid &gr,
+int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
                const katsevich_options &opts, PlanHost &P, std::string &err,
                const DevicePiSolve *dev) {
+    auto bad = [&](const std::string &m) { err = m; return KATS_EINVAL_GEOMETRY; };
+    if (opts.flags & ~KATS_FLAG_HALF_SAMPLE_DERIVATIVE) return bad("unknown option flags");
+    // Half-sample derivative: eq. Deriv is taken at the centre of each 2 x 2 cell of the
+    // sinogram's (lambda, alpha) samples, so the filtered data live on views lambda_{n+1/2}
+    // and columns alpha_{c+1/2}: one view and one column fewer, the same column offset
+    // (columns are centred on the detector).  Every later step runs on that grid; only the
+    // derivative reads the sinogram's own grid.
+    P.half = (opts.flags & KATS_FLAG_HALF_SAMPLE_DERIVATIVE) != 0;
+    P.sino_views = g_in.n_views;
+    P.sino_cols = g_in.det_cols;
+    katsevich_geometry g = g_in;
+    if (P.half) {
+        if (g_in.n_views < 4 || g_in.det_cols < 3)
+            return bad("the half-sample derivative needs n_views >= 4 and det_cols >= 3");
+        if (g_in.views_per_turn < 4) return bad("views_per_turn must be >= 4");
+        g.lambda_first += kPi / g_in.views_per_turn;
+        g.det_cols -= 1;
+        g.n_views -= 1;
+    }
     P.geom = g;
     P.grid = gr;
     P.opts = opts;
     // ------------------------------------------------------------------ validation
-    auto bad = [&](const std::string &m) { err = m; return KATS_EINVAL_GEOMETRY; };
     if (!(g.R > 0) || !(g.D > 0) || !(g.feed_per_turn > 0)) return bad("R, D and feed_per_turn must be > 0");
     if (g.views_per_turn < 4) return bad("views_per_turn must be >= 4");
     if (g.n_views < 3) return bad("n_views must be >= 3");

@@ -70,7 +70,10 @@ struct TableLayout {
 };
 
 struct PlanHost {
-    katsevich_geometry geom{};
+    katsevich_geometry geom{};       // grid of the filtered data (see build_plan)
+    bool half = false;               // half-sample derivative (KATS_FLAG_HALF_SAMPLE_DERIVATIVE)
+    int64_t sino_views = 0;          // sinogram views and columns as acquired
+    int sino_cols = 0;
     katsevich_grid grid{};
     katsevich_options opts{};
 

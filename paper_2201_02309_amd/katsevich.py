@@ -51,8 +51,10 @@ class _Info(ctypes.Structure):
                 ("window_views", c_int32), ("window_lo", c_int32), ("fft_len", c_int32),
                 ("commensurate", c_int32), ("gf_rows", c_int32), ("gf_cols", c_int32),
                 ("atan_degree", c_int32), ("bp_slices", c_int32), ("bp_box_rows", c_int32),
-                ("bp_box_cols", c_int32), ("reserved", c_int32)]
+                ("bp_box_cols", c_int32), ("half_sample", c_int32)]
 
+
+FLAG_HALF_SAMPLE_DERIVATIVE = 1   # KATS_FLAG_HALF_SAMPLE_DERIVATIVE (include/katsevich.h)
 
 # table id -> (C enum, numpy dtype, shape key)
 TABLES = {
@@ -144,14 +146,18 @@ class Plan:
     geom / grid: dicts with the fields of katsevich_geometry / katsevich_grid."""
 
     def __init__(self, geom: dict, grid: dict, n_psi: int = 0, n_threads: int = 0,
-                 bind: bool = True, device=None, bp_slices: int = 0, gpu_plan: bool = False):
+                 bind: bool = True, device=None, bp_slices: int = 0, gpu_plan: bool = False,
+                 half_sample: bool = False):
         """gpu_plan: solve the PI lines on the GPU (katsevich_plan_device) with a scratch
-        tensor on `device` and its current stream; otherwise everything on the host."""
+        tensor on `device` and its current stream; otherwise everything on the host.
+        half_sample: KATS_FLAG_HALF_SAMPLE_DERIVATIVE (derivative at the centres of the
+        sinogram's 2 x 2 (lambda, alpha) cells)."""
         self._lib = load_library()
         self.geom = dict(geom)
         self.grid = dict(grid)
         self._h = c_void_p()
-        opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads), flags=0,
+        opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads),
+                        flags=FLAG_HALF_SAMPLE_DERIVATIVE if half_sample else 0,
                         bp_slices=int(bp_slices))
         g, gr = _geom_struct(geom), _grid_struct(grid)
         if gpu_plan:
@@ -203,8 +209,9 @@ class Plan:
     def export(self, name: str) -> np.ndarray:
         which, dtype, shape_key = TABLES[name]
         i, g, gr = self.info, self.geom, self.grid
-        shape = {"psi_cols": (i["n_psi"], g["det_cols"]),
-                 "rows_cols": (g["det_rows"], g["det_cols"]),
+        cols = int(g["det_cols"]) - int(i["half_sample"])     # columns of the filtered grid
+        shape = {"psi_cols": (i["n_psi"], cols),
+                 "rows_cols": (g["det_rows"], cols),
                  "tab": (i["n_table_slices"], gr["ny"], gr["nx"]),
                  "vol": (gr["nz"], gr["ny"], gr["nx"])}[shape_key]
         out = np.empty(shape, dtype=dtype)

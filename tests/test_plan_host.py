@@ -62,6 +62,19 @@ def test_rejects_invalid_geometry(field, value):
     assert e.value.status == -2
 
 
+def test_rejects_unknown_flags():
+    wl = configs.tiny()
+    lib = pk.load_library()
+    import ctypes
+    from paper_2201_02309_amd.katsevich import _Options, _geom_struct, _grid_struct
+    h = ctypes.c_void_p()
+    opts = _Options(n_psi=0, n_threads=0, flags=6, bp_slices=0)
+    st = lib.katsevich_plan(ctypes.byref(_geom_struct(wl.geom.as_dict())),
+                            ctypes.byref(_grid_struct(wl.grid.as_dict())), ctypes.byref(opts),
+                            ctypes.byref(h))
+    assert st == -2 and b"flags" in lib.katsevich_last_error()
+
+
 def test_rejects_invalid_grid():
     wl = configs.config1()
     gr = wl.grid.as_dict()
@@ -80,10 +93,11 @@ def test_compute_on_unbound_plan_is_an_error():
     assert b"not bound" in p._lib.katsevich_last_error()
 
 
-def _compare_tables(wl, n_sample=None, seed=0):
-    scan = O.Scan(wl.geom.as_dict(), wl.n_psi)
+def _compare_tables(wl, n_sample=None, seed=0, half=False):
+    g = wl.geom.as_dict()
+    scan = O.Scan(O.half_sample_geometry(g) if half else g, wl.n_psi)
     gr = wl.grid.as_dict()
-    p = _plan(wl, n_psi=wl.n_psi)
+    p = _plan(wl, n_psi=wl.n_psi, half_sample=half)
     r0, t = O.forward_rebin_table(scan)
     assert np.array_equal(r0, p.export("fr_row"))
     assert np.abs(t - p.export("fr_weight")).max() < 1e-12
@@ -119,9 +133,12 @@ def _compare_tables(wl, n_sample=None, seed=0):
     return p, scan
 
 
-def test_tables_bit_exact_parity_config():
+@pytest.mark.parametrize("half", [False, True])
+def test_tables_bit_exact_parity_config(half):
+    """half: the half-sample derivative plan builds its tables on the cell-centre grid."""
     wl = configs.config1()
-    p, scan = _compare_tables(wl)
+    p, scan = _compare_tables(wl, half=half)
+    assert p.info["half_sample"] == int(half)
     gr = wl.grid.as_dict()
     tab = O.pitch_tables(scan, gr)
     assert p.info["window_lo"] == tab["n_lo"]
