@@ -5,3 +5,4 @@ TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and 
 (the HIP library and its Python binding) never calls it and shares no code with it.
 """
 from .katsevich_oracle import *  # noqa: F401,F403
+from . import data_oracle  # noqa: F401,E402
