@@ -216,6 +216,44 @@ int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *cons
 int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, float *d_grad_sino,
                              void *d_ws, uint64_t ws_bytes, void *stream);
 
+/* ---- Sparse-detector data path and image metrics (Sec. III-C data preparation, Sec. IV
+ * metrics).  Plan-free, asynchronous on stream, no device allocation; device buffers are
+ * the caller's.  Errors: KATS_EINVAL (null pointer, bad size), KATS_EWORKSPACE, KATS_EHIP. */
+
+/* Interpolate a sparse-detector sinogram back to the full column grid: the sparse data
+ * hold columns 0, step, 2 step, ... of a detector with cols columns (Sec. III-C keeps every
+ * 4th), d_sparse float32 [n_lines][ns] with ns = ceil(cols / step), n_lines = n_views *
+ * rows; d_full float32 [n_lines][cols] gets the linear interpolation in alpha between
+ * neighbouring kept columns, and the last kept column's value beyond it. */
+int katsevich_sparse_upsample(const float *d_sparse, float *d_full, int64_t n_lines, int32_t cols,
+                              int32_t step, void *stream);
+
+/* Device scratch (bytes) of katsevich_max and katsevich_rmse_ssim (fixed, 256-byte
+ * aligned buffer, any n). */
+uint64_t katsevich_data_scratch_bytes(void);
+
+/* d_max[0] = max of the n values of d_x (n >= 1); deterministic. */
+int katsevich_max(const float *d_x, uint64_t n, float *d_max, void *d_scratch,
+                  uint64_t scratch_bytes, void *stream);
+
+/* Noisy sinogram of Sec. III-C: with M = d_max[0] (the maximum of d_in, e.g. from
+ * katsevich_max) each element becomes M log(I0 / counts), counts = lambda + sqrt(lambda) z1
+ * + sqrt(var) z2, lambda = I0 exp(-g / M): Poisson photon counts by their normal limit
+ * (lambda >= I0 / e here) plus Gaussian electronic noise of mean 0 and variance var,
+ * counts below 1 raised to 1.  z1, z2: Box-Muller transform of the 24-bit uniforms
+ * u1 = ((x0 >> 40) + 1) 2^-24, u2 = (x1 >> 40) 2^-24, where (x0, x1, ., .) is the
+ * Philox4x64-10 block of counter (element index, 0, 0, 0) and key (seed, 0).  d_out may
+ * equal d_in. */
+int katsevich_add_noise(const float *d_in, float *d_out, uint64_t n, const float *d_max, double I0,
+                        double var, uint64_t seed, void *stream);
+
+/* d_result[0] = RMSE = sqrt(sum (f - ref)^2 / n); d_result[1] = SSIM of the two whole
+ * images (one window): (2 mu_f mu_r + c1)(2 cov + c2) / ((mu_f^2 + mu_r^2 + c1)(var_f +
+ * var_r + c2)), population moments, c1 = (0.01 (max ref - min ref))^2, c2 = (0.03 (max
+ * ref - min ref))^2 (Sec. IV).  Float64 accumulation, two passes, deterministic. */
+int katsevich_rmse_ssim(const float *d_f, const float *d_ref, uint64_t n, double *d_result,
+                        void *d_scratch, uint64_t scratch_bytes, void *stream);
+
 /* Free a plan (NULL is ignored).  Device buffers stay with the caller. */
 void katsevich_plan_destroy(katsevich_plan_t plan);
 

@@ -349,6 +349,56 @@ int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, flo
     return KATS_OK;
 }
 
+int katsevich_sparse_upsample(const float *d_sparse, float *d_full, int64_t n_lines, int32_t cols,
+                              int32_t step, void *stream) {
+    g_err.clear();
+    if (!d_sparse || !d_full) return fail(KATS_EINVAL, "katsevich_sparse_upsample: null pointer");
+    if (n_lines < 0 || cols < 1 || step < 1)
+        return fail(KATS_EINVAL, "katsevich_sparse_upsample: need n_lines >= 0, cols >= 1, step >= 1");
+    const int ns = (cols + step - 1) / step;
+    hipError_t e = kats::launch_upsample(d_sparse, d_full, n_lines, cols, ns, step,
+                                          static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_sparse_upsample: launch");
+    return KATS_OK;
+}
+
+uint64_t katsevich_data_scratch_bytes(void) { return kats::data_scratch_bytes(); }
+
+int katsevich_max(const float *d_x, uint64_t n, float *d_max, void *d_scratch, uint64_t scratch_bytes,
+                  void *stream) {
+    g_err.clear();
+    if (!d_x || !d_max || !d_scratch || n < 1) return fail(KATS_EINVAL, "katsevich_max: null pointer or n < 1");
+    if (scratch_bytes < kats::data_scratch_bytes()) return fail(KATS_EWORKSPACE, "katsevich_max: scratch too small");
+    if (!aligned256(d_scratch)) return fail(KATS_EINVAL, "katsevich_max: scratch not 256-byte aligned");
+    hipError_t e = kats::launch_max(d_x, n, d_max, d_scratch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_max: launch");
+    return KATS_OK;
+}
+
+int katsevich_add_noise(const float *d_in, float *d_out, uint64_t n, const float *d_max, double I0,
+                        double var, uint64_t seed, void *stream) {
+    g_err.clear();
+    if (!d_in || !d_out || !d_max) return fail(KATS_EINVAL, "katsevich_add_noise: null pointer");
+    if (!(I0 > 1.0) || !(var >= 0.0)) return fail(KATS_EINVAL, "katsevich_add_noise: need I0 > 1 and var >= 0");
+    hipError_t e = kats::launch_noise(d_in, d_out, n, d_max, (float)I0, (float)std::sqrt(var), seed,
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_add_noise: launch");
+    return KATS_OK;
+}
+
+int katsevich_rmse_ssim(const float *d_f, const float *d_ref, uint64_t n, double *d_result,
+                        void *d_scratch, uint64_t scratch_bytes, void *stream) {
+    g_err.clear();
+    if (!d_f || !d_ref || !d_result || !d_scratch || n < 1)
+        return fail(KATS_EINVAL, "katsevich_rmse_ssim: null pointer or n < 1");
+    if (scratch_bytes < kats::data_scratch_bytes())
+        return fail(KATS_EWORKSPACE, "katsevich_rmse_ssim: scratch too small");
+    if (!aligned256(d_scratch)) return fail(KATS_EINVAL, "katsevich_rmse_ssim: scratch not 256-byte aligned");
+    hipError_t e = kats::launch_rmse_ssim(d_f, d_ref, n, d_result, d_scratch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_rmse_ssim: launch");
+    return KATS_OK;
+}
+
 int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *const *d_gF,
                                 float *const *d_vol, int n, void *stream) {
     g_err.clear();

@@ -1,0 +1,274 @@
+// Data path of the paper's sparse-detector experiments (Sec. III-C) and its image metrics
+// (Sec. IV): keep every step-th detector column, interpolate the sinogram back to the full
+// column grid, simulate photon and electronic noise, and compare a reconstruction with a
+// reference by RMSE and SSIM.
+//
+//   k_upsample   linear interpolation in alpha between the kept columns (the last kept
+//                column is held beyond its position)
+//   k_noise      counts = I0 exp(-g/M) + sqrt(.) z1 + sqrt(var) z2 (Poisson counts by their
+//                normal limit, Gaussian electronic noise), g_in = M log(I0 / counts);
+//                z1, z2 from one Philox4x64-10 block per element (counter = element index,
+//                key = (seed, 0)) through the Box-Muller transform
+//   k_max_*, k_moments_*  deterministic two-level reductions (block partials in caller
+//                scratch, then one block in a fixed order), float64 accumulation
+// All kernels are elementwise or reductions that stream their inputs once.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace kats {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------- upsampling
+__global__ __launch_bounds__(kThreads) void k_upsample(const float *__restrict__ sp, float *__restrict__ full,
+                                                       long long lines, int cols, int ns, int step) {
+    const long long line = blockIdx.y + (long long)gridDim.y * blockIdx.z;   // (view, row)
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (line >= lines || c >= cols) return;
+    const float *s = sp + line * ns;
+    const int j = c / step;
+    const int k = c - j * step;
+    float v;
+    if (j + 1 < ns) {
+        const float a = s[j], b = s[j + 1];
+        v = fmaf((float)k / (float)step, b - a, a);
+    } else {
+        v = s[ns - 1];
+    }
+    full[line * cols + c] = v;
+}
+
+// ---------------------------------------------------------------- Philox4x64-10
+struct U64x4 {
+    uint64_t v[4];
+};
+
+__device__ inline void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
+    lo = a * b;
+    hi = __umul64hi(a, b);
+}
+
+// Philox4x64 with 10 rounds (Salmon et al., SC'11): round multipliers 0xD2E7470EE14C6C93 and
+// 0xCA5A826395121157, key increments (Weyl) 0x9E3779B97F4A7C15 and 0xBB67AE8584CAA73B.
+__device__ inline U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(0xD2E7470EE14C6C93ull, c.v[0], hi0, lo0);
+        mulhilo64(0xCA5A826395121157ull, c.v[2], hi1, lo1);
+        U64x4 n;
+        n.v[0] = hi1 ^ c.v[1] ^ k0;
+        n.v[1] = lo1;
+        n.v[2] = hi0 ^ c.v[3] ^ k1;
+        n.v[3] = lo0;
+        c = n;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kThreads) void k_noise(const float *__restrict__ in, float *__restrict__ out,
+                                                    unsigned long long n, const float *__restrict__ d_max,
+                                                    float I0, float sd_e, uint64_t seed) {
+    const unsigned long long e = (unsigned long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n) return;
+    const float M = *d_max;
+    U64x4 ctr;
+    ctr.v[0] = e;
+    ctr.v[1] = 0;
+    ctr.v[2] = 0;
+    ctr.v[3] = 0;
+    const U64x4 x = philox4x64_10(ctr, seed, 0);
+    // 24-bit uniforms: u1 in (0, 1], u2 in [0, 1)
+    const float u1 = (float)((x.v[0] >> 40) + 1) * 5.9604644775390625e-8f;
+    const float u2 = (float)(x.v[1] >> 40) * 5.9604644775390625e-8f;
+    const float rho = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincosf(6.28318530717958647692f * u2, &s, &c);
+    const float z1 = rho * c, z2 = rho * s;
+    const float lam = I0 * expf(-in[e] / M);
+    float counts = fmaf(sqrtf(lam), z1, lam) + sd_e * z2;
+    counts = fmaxf(counts, 1.0f);
+    out[e] = M * logf(I0 / counts);
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int kRedBlocks = 1024;     // partial sums per reduction (scratch of 8 doubles each)
+
+__device__ inline double block_sum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__device__ inline float block_max(float v, float *sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    return fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+}
+
+__global__ __launch_bounds__(kThreads) void k_max_partial(const float *__restrict__ x, unsigned long long n,
+                                                          float *__restrict__ part) {
+    __shared__ float sh[4];
+    float m = -INFINITY;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * kThreads)
+        m = fmaxf(m, x[i]);
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kThreads) void k_max_final(const float *__restrict__ part, int np,
+                                                        float *__restrict__ out) {
+    __shared__ float sh[4];
+    float m = -INFINITY;
+    for (int i = threadIdx.x; i < np; i += kThreads) m = fmaxf(m, part[i]);
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) *out = m;
+}
+
+// pass 1 (mu == nullptr): sum f, sum g, sum (f-g)^2, min g, max g
+// pass 2: sum (f-mu_f)^2, sum (g-mu_g)^2, sum (f-mu_f)(g-mu_g)
+__global__ __launch_bounds__(kThreads) void k_moments_partial(const float *__restrict__ f,
+                                                              const float *__restrict__ g,
+                                                              unsigned long long n,
+                                                              const double *__restrict__ mu,
+                                                              double *__restrict__ part) {
+    __shared__ double sh[4];
+    __shared__ float shf[4];
+    double a = 0.0, b = 0.0, c = 0.0;
+    float lo = INFINITY, hi = -INFINITY;
+    const double mf = mu ? mu[0] : 0.0, mg = mu ? mu[1] : 0.0;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * kThreads) {
+        const double x = f[i], y = g[i];
+        if (!mu) {
+            a += x;
+            b += y;
+            c += (x - y) * (x - y);
+            lo = fminf(lo, g[i]);
+            hi = fmaxf(hi, g[i]);
+        } else {
+            a += (x - mf) * (x - mf);
+            b += (y - mg) * (y - mg);
+            c += (x - mf) * (y - mg);
+        }
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    c = block_sum(c, sh);
+    lo = -block_max(-lo, shf);
+    hi = block_max(hi, shf);
+    if (threadIdx.x == 0) {
+        double *p = part + (size_t)blockIdx.x * 5;
+        p[0] = a;
+        p[1] = b;
+        p[2] = c;
+        p[3] = lo;
+        p[4] = hi;
+    }
+}
+
+// out: pass 1 -> mu[0..1] = means, stats[0] = sum (f-g)^2, stats[1..2] = min/max g;
+//      pass 2 -> RMSE and SSIM into result[0..1]
+__global__ __launch_bounds__(kThreads) void k_moments_final(const double *__restrict__ part, int np,
+                                                            unsigned long long n, int pass,
+                                                            double *__restrict__ mu,
+                                                            double *__restrict__ result) {
+    __shared__ double sh[4];
+    __shared__ float shf[4];
+    double a = 0.0, b = 0.0, c = 0.0;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int i = threadIdx.x; i < np; i += kThreads) {
+        const double *p = part + (size_t)i * 5;
+        a += p[0];
+        b += p[1];
+        c += p[2];
+        lo = fminf(lo, (float)p[3]);
+        hi = fmaxf(hi, (float)p[4]);
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    c = block_sum(c, sh);
+    lo = -block_max(-lo, shf);
+    hi = block_max(hi, shf);
+    if (threadIdx.x != 0) return;
+    const double dn = (double)n;
+    if (pass == 1) {
+        mu[0] = a / dn;
+        mu[1] = b / dn;
+        mu[2] = c;            // sum of squared differences
+        mu[3] = lo;
+        mu[4] = hi;
+        return;
+    }
+    const double vf = a / dn, vg = b / dn, cov = c / dn;
+    const double range = mu[4] - mu[3];
+    const double c1 = (0.01 * range) * (0.01 * range), c2 = (0.03 * range) * (0.03 * range);
+    result[0] = sqrt(mu[2] / dn);
+    result[1] = (2.0 * mu[0] * mu[1] + c1) * (2.0 * cov + c2) /
+                ((mu[0] * mu[0] + mu[1] * mu[1] + c1) * (vf + vg + c2));
+}
+
+int red_blocks(unsigned long long n) {
+    const unsigned long long b = (n + kThreads * 16ull - 1) / (kThreads * 16ull);
+    return (int)(b < 1 ? 1 : (b > (unsigned long long)kRedBlocks ? kRedBlocks : b));
+}
+
+}  // namespace
+
+uint64_t data_scratch_bytes() { return (uint64_t)kRedBlocks * 5 * sizeof(double) + 256; }
+
+hipError_t launch_upsample(const float *sp, float *full, long long lines, int cols, int ns, int step,
+                           hipStream_t s) {
+    if (lines <= 0 || cols <= 0) return hipSuccess;
+    const unsigned gy = (unsigned)(lines < 65535 ? lines : 65535);
+    const unsigned gz = (unsigned)((lines + gy - 1) / gy);
+    hipLaunchKernelGGL(k_upsample, dim3((cols + kThreads - 1) / kThreads, gy, gz), dim3(kThreads), 0, s,
+                       sp, full, lines, cols, ns, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_max(const float *x, unsigned long long n, float *out, void *scratch, hipStream_t s) {
+    const int nb = red_blocks(n);
+    float *part = static_cast<float *>(scratch);
+    hipLaunchKernelGGL(k_max_partial, dim3(nb), dim3(kThreads), 0, s, x, n, part);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kThreads), 0, s, part, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise(const float *in, float *out, unsigned long long n, const float *d_max, float I0,
+                        float sd_e, uint64_t seed, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_noise, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       in, out, n, d_max, I0, sd_e, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_rmse_ssim(const float *f, const float *g, unsigned long long n, double *result,
+                            void *scratch, hipStream_t s) {
+    const int nb = red_blocks(n);
+    double *part = static_cast<double *>(scratch);
+    double *mu = part + (size_t)kRedBlocks * 5;           // 5 doubles after the partials
+    hipLaunchKernelGGL(k_moments_partial, dim3(nb), dim3(kThreads), 0, s, f, g, n, (const double *)nullptr, part);
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kThreads), 0, s, (const double *)part, nb, n, 1, mu,
+                       result);
+    hipLaunchKernelGGL(k_moments_partial, dim3(nb), dim3(kThreads), 0, s, f, g, n, (const double *)mu, part);
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kThreads), 0, s, (const double *)part, nb, n, 2, mu,
+                       result);
+    return hipGetLastError();
+}
+
+}  // namespace kats

@@ -48,6 +48,16 @@ struct KParams {
 
 KParams make_params(const PlanHost &P);
 
+// Sparse-detector data path and image metrics (data.hip).
+uint64_t data_scratch_bytes();
+hipError_t launch_upsample(const float *sp, float *full, long long lines, int cols, int ns, int step,
+                           hipStream_t s);
+hipError_t launch_max(const float *x, unsigned long long n, float *out, void *scratch, hipStream_t s);
+hipError_t launch_noise(const float *in, float *out, unsigned long long n, const float *d_max, float I0,
+                        float sd_e, uint64_t seed, hipStream_t s);
+hipError_t launch_rmse_ssim(const float *f, const float *g, unsigned long long n, double *result,
+                            void *scratch, hipStream_t s);
+
 // PI lines (lambda_i, lambda_o) of every voxel of the first n_tab slices, float64, into
 // d_li / d_lo [n_tab][ny][nx].
 hipError_t launch_pi_solve(const katsevich_geometry &g, const katsevich_grid &gr, double h,

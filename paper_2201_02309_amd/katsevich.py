@@ -69,7 +69,9 @@ EXPORTED = ["katsevich_plan", "katsevich_plan_query", "katsevich_plan_bind",
             "katsevich_plan_export", "katsevich_recon", "katsevich_filter",
             "katsevich_backproject", "katsevich_recon_backward", "katsevich_backproject_batch",
             "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error",
-            "katsevich_plan_device", "katsevich_plan_device_scratch_bytes"]
+            "katsevich_plan_device", "katsevich_plan_device_scratch_bytes",
+            "katsevich_sparse_upsample", "katsevich_data_scratch_bytes", "katsevich_max",
+            "katsevich_add_noise", "katsevich_rmse_ssim"]
 
 _lib = None
 
@@ -100,6 +102,18 @@ def load_library(path: str = LIB_PATH):
     lib.katsevich_plan_device.restype = c_int
     lib.katsevich_plan_device_scratch_bytes.argtypes = [POINTER(_Geometry), POINTER(_Grid)]
     lib.katsevich_plan_device_scratch_bytes.restype = c_uint64
+    lib.katsevich_sparse_upsample.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p]
+    lib.katsevich_sparse_upsample.restype = c_int
+    lib.katsevich_data_scratch_bytes.argtypes = []
+    lib.katsevich_data_scratch_bytes.restype = c_uint64
+    lib.katsevich_max.argtypes = [c_void_p, c_uint64, c_void_p, c_void_p, c_uint64, c_void_p]
+    lib.katsevich_max.restype = c_int
+    lib.katsevich_add_noise.argtypes = [c_void_p, c_void_p, c_uint64, c_void_p, c_double, c_double,
+                                        c_uint64, c_void_p]
+    lib.katsevich_add_noise.restype = c_int
+    lib.katsevich_rmse_ssim.argtypes = [c_void_p, c_void_p, c_uint64, c_void_p, c_void_p, c_uint64,
+                                        c_void_p]
+    lib.katsevich_rmse_ssim.restype = c_int
     lib.katsevich_plan_destroy.argtypes = [c_void_p]
     lib.katsevich_plan_destroy.restype = None
     lib.katsevich_status_string.argtypes = [c_int]
@@ -333,6 +347,90 @@ def backproject_batch(plans, gFs, vols=None):
     hv = arr(*[v.data_ptr() for v in vols])
     _check(lib, lib.katsevich_backproject_batch(hp, hg, hv, n, _stream_handle(gFs[0].device)))
     return vols
+
+
+# ---------------------------------------------------------------- data path and metrics
+def _f32(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise KatsevichError(-1, f"{name}: expected a contiguous float32 CUDA tensor")
+    return t
+
+
+def _data_scratch(device):
+    import torch
+    lib = load_library()
+    return torch.empty(max(int(lib.katsevich_data_scratch_bytes()), 256), dtype=torch.uint8,
+                       device=device)
+
+
+def sparse_upsample(sparse, cols: int, step: int = 4, out=None):
+    """katsevich_sparse_upsample: [..., ceil(cols/step)] sparse columns -> [..., cols]."""
+    import torch
+    _f32(sparse, "sparse")
+    ns = (int(cols) + int(step) - 1) // int(step)
+    if sparse.shape[-1] != ns:
+        raise KatsevichError(-3, f"sparse: last dimension {sparse.shape[-1]} != ceil(cols/step) = {ns}")
+    shape = tuple(sparse.shape[:-1]) + (int(cols),)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=sparse.device)
+    _f32(out, "out")
+    if tuple(out.shape) != shape:
+        raise KatsevichError(-3, f"out: shape {tuple(out.shape)} != {shape}")
+    lib = load_library()
+    _check(lib, lib.katsevich_sparse_upsample(c_void_p(sparse.data_ptr()), c_void_p(out.data_ptr()),
+                                              c_int64(sparse.numel() // ns), c_int32(int(cols)),
+                                              c_int32(int(step)), _stream_handle(sparse.device)))
+    return out
+
+
+def max_value(x, scratch=None):
+    """katsevich_max: device float32 tensor [1] holding max(x)."""
+    import torch
+    _f32(x, "x")
+    scratch = _data_scratch(x.device) if scratch is None else scratch
+    out = torch.empty(1, dtype=torch.float32, device=x.device)
+    lib = load_library()
+    _check(lib, lib.katsevich_max(c_void_p(x.data_ptr()), c_uint64(x.numel()), c_void_p(out.data_ptr()),
+                                  c_void_p(scratch.data_ptr()), c_uint64(scratch.numel()),
+                                  _stream_handle(x.device)))
+    return out
+
+
+def add_noise(g, I0: float = 1e5, var: float = 0.5, seed: int = 0, d_max=None, out=None):
+    """katsevich_add_noise (Sec. III-C noise model); d_max defaults to max_value(g)."""
+    import torch
+    _f32(g, "g")
+    d_max = max_value(g) if d_max is None else d_max
+    if out is None:
+        out = torch.empty_like(g)
+    _f32(out, "out")
+    if out.shape != g.shape:
+        raise KatsevichError(-3, "out: shape differs from g")
+    lib = load_library()
+    _check(lib, lib.katsevich_add_noise(c_void_p(g.data_ptr()), c_void_p(out.data_ptr()),
+                                        c_uint64(g.numel()), c_void_p(d_max.data_ptr()),
+                                        c_double(I0), c_double(var), c_uint64(int(seed)),
+                                        _stream_handle(g.device)))
+    return out
+
+
+def rmse_ssim(f, ref, scratch=None, result=None):
+    """katsevich_rmse_ssim: device float64 tensor [2] = (RMSE, SSIM) of f against ref."""
+    import torch
+    _f32(f, "f")
+    _f32(ref, "ref")
+    if f.shape != ref.shape:
+        raise KatsevichError(-3, "f and ref differ in shape")
+    scratch = _data_scratch(f.device) if scratch is None else scratch
+    result = torch.empty(2, dtype=torch.float64, device=f.device) if result is None else result
+    lib = load_library()
+    _check(lib, lib.katsevich_rmse_ssim(c_void_p(f.data_ptr()), c_void_p(ref.data_ptr()),
+                                        c_uint64(f.numel()), c_void_p(result.data_ptr()),
+                                        c_void_p(scratch.data_ptr()), c_uint64(scratch.numel()),
+                                        _stream_handle(f.device)))
+    return result
 
 
 def recon_backward(plan: Plan, grad_vol, out=None, ws=None):

@@ -1,0 +1,111 @@
+"""GPU parity of the sparse-detector data path and the metrics (katsevich_sparse_upsample,
+katsevich_max, katsevich_add_noise, katsevich_rmse_ssim) against oracle/data_oracle.py, and
+the whole chain of the paper's sparse-and-noisy experiment on the parity case."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import data_oracle as D
+from synth import configs, phantom
+
+torch = pytest.importorskip("torch")
+K = pytest.importorskip("paper_2201_02309_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def case():
+    wl = configs.config1()
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    return wl, geom, gr, phantom.project(ph, geom).astype(np.float32)
+
+
+@pytest.mark.parametrize("cols,step", [(128, 4), (131, 4), (37, 3), (5, 8)])
+def test_sparse_upsample_parity(case, cols, step):
+    dev = _dev()
+    rng = np.random.default_rng(cols)
+    sp = rng.uniform(0, 50, size=(33, 5, (cols + step - 1) // step)).astype(np.float32)
+    got = K.sparse_upsample(torch.from_numpy(sp).to(dev), cols, step).cpu().numpy()
+    ref = D.sparse_upsample(sp.astype(np.float64), cols, step)
+    err = np.abs(got - ref).max()
+    print(f"[parity] upsample cols {cols} step {step}: max-abs {err:.3e}", flush=True)
+    assert np.array_equal(got[..., ::step], sp)              # kept columns exactly
+    assert err <= 2e-6 * np.abs(ref).max()
+
+
+def test_max_is_exact(case):
+    dev = _dev()
+    _, _, _, sino = case
+    x = torch.from_numpy(sino).to(dev)
+    m = K.max_value(x).item()
+    assert m == float(sino.max())
+    y = torch.from_numpy(-np.abs(sino[:3, :, :7]).copy()).to(dev)     # all <= 0, ragged size
+    assert K.max_value(y).item() == float(y.cpu().numpy().max())
+
+
+def test_noise_parity_and_determinism(case):
+    dev = _dev()
+    _, _, _, sino = case
+    g = torch.from_numpy(sino).to(dev)
+    a = K.add_noise(g, I0=1e5, var=0.5, seed=1234)
+    b = K.add_noise(g, I0=1e5, var=0.5, seed=1234)
+    c = K.add_noise(g, I0=1e5, var=0.5, seed=1235)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and not torch.equal(a, c)
+    M = float(sino.max())
+    ref = D.add_noise(sino.astype(np.float64), M=M, I0=1e5, var=0.5, seed=1234)
+    got = a.cpu().numpy().astype(np.float64)
+    noise_ref = ref - sino
+    rel = np.linalg.norm((got - sino) - noise_ref) / np.linalg.norm(noise_ref)
+    mx = np.abs(got - ref).max()
+    print(f"[parity] noise: noise-part rel-L2 {rel:.3e}, max-abs {mx:.3e} (M {M:.2f})", flush=True)
+    assert rel <= 1e-4 and mx <= 2e-5 * M
+
+
+def test_rmse_ssim_parity(case):
+    dev = _dev()
+    rng = np.random.default_rng(4)
+    ref = rng.uniform(0, 1, size=(16, 33, 29)).astype(np.float32)
+    f = (ref + 0.1 * rng.normal(size=ref.shape)).astype(np.float32)
+    r = K.rmse_ssim(torch.from_numpy(f).to(dev), torch.from_numpy(ref).to(dev)).cpu().numpy()
+    e_rmse, e_ssim = D.rmse(f, ref), D.ssim(f, ref)
+    print(f"[parity] metrics: rmse {r[0]:.12g} vs {e_rmse:.12g}, ssim {r[1]:.12g} vs {e_ssim:.12g}",
+          flush=True)
+    assert abs(r[0] - e_rmse) <= 1e-12 * e_rmse and abs(r[1] - e_ssim) <= 1e-12
+
+
+def test_sparse_noisy_chain_parity(case):
+    """Sec. III-C chain on the parity case: every 4th column, upsampling, noise, Katsevich
+    reconstruction, RMSE / SSIM against the reconstruction of the full noise-free data,
+    GPU against the oracle at every stage's output."""
+    dev = _dev()
+    wl, geom, gr, sino = case
+    step, cols = 4, geom["det_cols"]
+    sp = np.ascontiguousarray(sino[..., ::step])
+    g_up = K.sparse_upsample(torch.from_numpy(sp).to(dev), cols, step)
+    g_in = K.add_noise(g_up, I0=1e5, var=0.5, seed=77)
+    plan = K.Plan(geom, gr, device=0)
+    f_in = K.recon(plan, g_in)
+    f_gt = K.recon(plan, torch.from_numpy(sino).to(dev))
+    m = K.rmse_ssim(f_in, f_gt).cpu().numpy()
+
+    up_ref = D.sparse_upsample(sp.astype(np.float64), cols, step)
+    in_ref = D.add_noise(up_ref, M=up_ref.max(), I0=1e5, var=0.5, seed=77)
+    scan = O.Scan(geom)
+    tab = O.pitch_tables(scan, gr)
+    ftab = O.FilterTables(scan)
+    fi_ref, valid = O.recon(scan, gr, in_ref.astype(np.float32), tables=tab, ftables=ftab)
+    fg_ref, _ = O.recon(scan, gr, sino, tables=tab, ftables=ftab)
+    r_rmse, r_ssim = D.rmse(fi_ref, fg_ref), D.ssim(fi_ref, fg_ref)
+    print(f"[parity] chain: GPU rmse {m[0]:.6g} ssim {m[1]:.6g} | oracle rmse {r_rmse:.6g} "
+          f"ssim {r_ssim:.6g}", flush=True)
+    assert 0 < m[0] and m[1] < 1
+    assert abs(m[0] - r_rmse) <= 1e-3 * r_rmse and abs(m[1] - r_ssim) <= 1e-4
