@@ -139,6 +139,49 @@ def serving_bench(n_requests=24, rate=20.0, budget=200e9):
     return out
 
 
+def data_path_bench(sino, vol, ref_vol, reps=5):
+    """Sec. III-C data path on the whole clinical sinogram (every 4th column kept, linear
+    upsampling, Philox noise) and the Sec. IV metrics on the volume: per-call time with HIP
+    events on the launch stream and the algorithmic HBM bytes of each call."""
+    import torch
+
+    import paper_2201_02309_amd as K
+    step, cols = 4, sino.shape[-1]
+    sp = sino[..., ::step].contiguous()                  # the sparse-detector acquisition
+    up = torch.empty_like(sino)
+    noisy = torch.empty_like(sino)
+    d_max = torch.empty(1, dtype=torch.float32, device=sino.device)
+    scratch = torch.empty(1 << 20, dtype=torch.uint8, device=sino.device)
+    res = torch.empty(2, dtype=torch.float64, device=sino.device)
+    n = sino.numel()
+    calls = {
+        "sparse_upsample": (lambda: K.sparse_upsample(sp, cols, step, out=up), 4 * (sp.numel() + n)),
+        "max": (lambda: K.max_value(up, scratch=scratch, out=d_max), 4 * n),
+        "add_noise": (lambda: K.add_noise(up, 1e5, 0.5, 7, d_max=d_max, out=noisy), 8 * n),
+        "rmse_ssim": (lambda: K.rmse_ssim(vol, ref_vol, scratch=scratch, result=res),
+                      2 * 2 * 4 * vol.numel()),
+    }
+    out = {"workload": f"clinical sinogram {tuple(sino.shape)} float32, sparse step {step}; "
+                       f"metrics on the {tuple(vol.shape)} volume",
+           "hbm_peak_GBps": 8000.0}
+    for name, (fn, nbytes) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[name] = {"ms": round(ms, 4), "algorithmic_GB": round(nbytes / 1e9, 4),
+                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(nbytes / (ms * 1e-3) / 8e12, 4)}
+    del sp, up, noisy, scratch
+    return out
+
+
 def _measured_traffic():
     """HBM bytes per backprojection launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (scaled by a plain-copy calibration), or None when the kernel or
@@ -238,6 +281,20 @@ def main():
     torch.cuda.synchronize()
     recon_ms = (time.perf_counter() - t1) * 1e3 / max(3, args.steps // 2)
 
+    # the half-sample derivative option (KATS_FLAG_HALF_SAMPLE_DERIVATIVE), same workload
+    plan_h = K.Plan(geom, gr, device=0, bp_slices=args.bp_slices, half_sample=True)
+    ws_h = plan_h.workspace()
+    for _ in range(2):
+        K.recon(plan_h, sino, out=vol, ws=ws_h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        K.recon(plan_h, sino, out=vol, ws=ws_h)
+    torch.cuda.synchronize()
+    half_ms = (time.perf_counter() - t1) * 1e3 / 5
+    plan_h.close()
+    del plan_h, ws_h
+
     # the adjoint (katsevich_recon_backward: sinogram cotangent of a volume cotangent)
     gvol = torch.randn_like(vol)
     gsino = torch.empty_like(sino)
@@ -278,6 +335,7 @@ def main():
         "stage_ms": {"filter": round(float(np.mean(filt_ms)), 4), "backproject": round(bp_avg, 4)},
         "recon_call_ms": round(recon_ms, 4),
         "adjoint_call_ms": round(adjoint_ms, 3),
+        "half_sample_recon_call_ms": round(half_ms, 4),
         "plan_build_s": round(t_plan, 3),
         "plan_build_gpu_pi_s": round(t_plan_gpu, 3),
         "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": round(achieved, 3),
@@ -285,6 +343,11 @@ def main():
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
                      "flop_per_update": BP_FLOP_PER_UPDATE},
     }
+    K.recon(plan, sino, out=vol, ws=ws)
+    ref_vol = vol.clone()
+    K.recon(plan, K.add_noise(sino, 1e5, 0.5, 3), out=vol, ws=ws)
+    out["data_path"] = data_path_bench(sino, vol, ref_vol)
+    del ref_vol
     if args.serve_requests > 0:
         gF = ws = None
         plan.release_workspace()

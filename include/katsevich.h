@@ -224,7 +224,8 @@ int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, flo
  * hold columns 0, step, 2 step, ... of a detector with cols columns (Sec. III-C keeps every
  * 4th), d_sparse float32 [n_lines][ns] with ns = ceil(cols / step), n_lines = n_views *
  * rows; d_full float32 [n_lines][cols] gets the linear interpolation in alpha between
- * neighbouring kept columns, and the last kept column's value beyond it. */
+ * neighbouring kept columns, and the last kept column's value beyond it (at most 2^34
+ * output samples). */
 int katsevich_sparse_upsample(const float *d_sparse, float *d_full, int64_t n_lines, int32_t cols,
                               int32_t step, void *stream);
 
@@ -241,9 +242,10 @@ int katsevich_max(const float *d_x, uint64_t n, float *d_max, void *d_scratch,
  * + sqrt(var) z2, lambda = I0 exp(-g / M): Poisson photon counts by their normal limit
  * (lambda >= I0 / e here) plus Gaussian electronic noise of mean 0 and variance var,
  * counts below 1 raised to 1.  z1, z2: Box-Muller transform of the 24-bit uniforms
- * u1 = ((x0 >> 40) + 1) 2^-24, u2 = (x1 >> 40) 2^-24, where (x0, x1, ., .) is the
- * Philox4x64-10 block of counter (element index, 0, 0, 0) and key (seed, 0).  d_out may
- * equal d_in. */
+ * u1 = ((a >> 40) + 1) 2^-24, u2 = (b >> 40) 2^-24, where elements 2k and 2k+1 take
+ * (a, b) = (x0, x1) and (x2, x3) of the Philox4x64-10 block of counter (k, 0, 0, 0) and
+ * key (seed, 0).  The transcendentals are the hardware's single-precision ones.  d_out
+ * may equal d_in. */
 int katsevich_add_noise(const float *d_in, float *d_out, uint64_t n, const float *d_max, double I0,
                         double var, uint64_t seed, void *stream);
 

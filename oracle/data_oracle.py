@@ -15,9 +15,10 @@ with the HIP library.
     where the two laws differ by O(lambda^-1/2) in distribution); counts below one photon
     are raised to 1;
   - the normal variates come from the counter-based generator Philox4x64-10 (Salmon et
-    al., SC'11): element e takes the block of counter (e, 0, 0, 0) and key (seed, 0), whose
-    first two words give the 24-bit uniforms u1 = ((x0 >> 40) + 1) 2^-24, u2 =
-    (x1 >> 40) 2^-24, and z1, z2 = sqrt(-2 ln u1) (cos, sin)(2 pi u2) (Box-Muller).
+    al., SC'11): elements 2b and 2b+1 share the block of counter (b, 0, 0, 0) and key
+    (seed, 0); the even one takes its words (x0, x1), the odd one (x2, x3), as the 24-bit
+    uniforms u1 = ((first >> 40) + 1) 2^-24, u2 = (second >> 40) 2^-24, and
+    z1, z2 = sqrt(-2 ln u1) (cos, sin)(2 pi u2) (Box-Muller).
 * Sec. IV metrics: RMSE = sqrt(||f - f_GT||^2 / n); SSIM of the whole image as one window
   with population means, variances and covariance and c1 = (0.01 range(f_GT))^2,
   c2 = (0.03 range(f_GT))^2 (the paper calls sigma a variance but squares it in the
@@ -83,11 +84,14 @@ def sparse_upsample(gs, cols, step=4):
 
 def normals(n, seed):
     """(z1, z2) of elements 0 .. n-1."""
-    ctr = np.zeros((n, 4), np.uint64)
-    ctr[:, 0] = np.arange(n, dtype=np.uint64)
+    nb = (n + 1) // 2
+    ctr = np.zeros((nb, 4), np.uint64)
+    ctr[:, 0] = np.arange(nb, dtype=np.uint64)
     x = philox4x64_10(ctr, (seed, 0))
-    u1 = ((x[:, 0] >> np.uint64(40)).astype(np.float64) + 1.0) * 2.0 ** -24
-    u2 = (x[:, 1] >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+    first = np.stack([x[:, 0], x[:, 2]], axis=1).ravel()[:n]       # even, odd elements
+    second = np.stack([x[:, 1], x[:, 3]], axis=1).ravel()[:n]
+    u1 = ((first >> np.uint64(40)).astype(np.float64) + 1.0) * 2.0 ** -24
+    u2 = (second >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
     rho = np.sqrt(-2.0 * np.log(u1))
     return rho * np.cos(2.0 * np.pi * u2), rho * np.sin(2.0 * np.pi * u2)
 

@@ -355,6 +355,8 @@ int katsevich_sparse_upsample(const float *d_sparse, float *d_full, int64_t n_li
     if (!d_sparse || !d_full) return fail(KATS_EINVAL, "katsevich_sparse_upsample: null pointer");
     if (n_lines < 0 || cols < 1 || step < 1)
         return fail(KATS_EINVAL, "katsevich_sparse_upsample: need n_lines >= 0, cols >= 1, step >= 1");
+    if ((uint64_t)n_lines * (((uint64_t)cols + 3) / 4) >= (1ull << 32))
+        return fail(KATS_EINVAL, "katsevich_sparse_upsample: more than 2^34 output samples");
     const int ns = (cols + step - 1) / step;
     hipError_t e = kats::launch_upsample(d_sparse, d_full, n_lines, cols, ns, step,
                                           static_cast<hipStream_t>(stream));

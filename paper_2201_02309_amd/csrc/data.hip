@@ -7,8 +7,9 @@
 //                column is held beyond its position)
 //   k_noise      counts = I0 exp(-g/M) + sqrt(.) z1 + sqrt(var) z2 (Poisson counts by their
 //                normal limit, Gaussian electronic noise), g_in = M log(I0 / counts);
-//                z1, z2 from one Philox4x64-10 block per element (counter = element index,
-//                key = (seed, 0)) through the Box-Muller transform
+//                z1, z2 through the Box-Muller transform from one Philox4x64-10 block per
+//                pair of elements (counter = pair index, key = (seed, 0)): words 0, 1 for
+//                the even element, 2, 3 for the odd one
 //   k_max_*, k_moments_*  deterministic two-level reductions (block partials in caller
 //                scratch, then one block in a fixed order), float64 accumulation
 // All kernels are elementwise or reductions that stream their inputs once.
@@ -25,22 +26,43 @@ namespace {
 constexpr int kThreads = 256;
 
 // ---------------------------------------------------------------- upsampling
+// Thread q takes output columns 4p .. 4p+3 (p = q mod slots) of line q / slots: one 32-bit
+// division per thread, the kept-column index advanced incrementally, one 16-byte store
+// when rows of the output are 16-byte aligned (cols a multiple of 4).
 __global__ __launch_bounds__(kThreads) void k_upsample(const float *__restrict__ sp, float *__restrict__ full,
-                                                       long long lines, int cols, int ns, int step) {
-    const long long line = blockIdx.y + (long long)gridDim.y * blockIdx.z;   // (view, row)
-    const int c = blockIdx.x * kThreads + threadIdx.x;
-    if (line >= lines || c >= cols) return;
-    const float *s = sp + line * ns;
-    const int j = c / step;
-    const int k = c - j * step;
-    float v;
-    if (j + 1 < ns) {
-        const float a = s[j], b = s[j + 1];
-        v = fmaf((float)k / (float)step, b - a, a);
-    } else {
-        v = s[ns - 1];
+                                                       unsigned lines, int cols, int ns, int step) {
+    const unsigned slots = ((unsigned)cols + 3u) / 4u;
+    const unsigned total = lines * slots;                      // < 2^32 (host check)
+    const bool vec = (cols & 3) == 0 && ((uintptr_t)full & 15) == 0;
+    const float inv_step = 1.0f / (float)step;
+    for (unsigned q = blockIdx.x * kThreads + threadIdx.x; q < total; q += gridDim.x * kThreads) {
+        const unsigned line = q / slots;
+        const int c0 = (int)(q - line * slots) * 4;
+        const float *s = sp + (size_t)line * ns;
+        int j = c0 / step, k = c0 - j * step;
+        float v[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (j + 1 < ns) {
+                const float a = s[j], b = s[j + 1];
+                v[t] = fmaf((float)k * inv_step, b - a, a);
+            } else {
+                v[t] = s[ns - 1];
+            }
+            if (++k == step) {
+                k = 0;
+                ++j;
+            }
+        }
+        float *o = full + (size_t)line * cols + c0;
+        if (vec) {
+            *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (c0 + t < cols) o[t] = v[t];
+        }
     }
-    full[line * cols + c] = v;
 }
 
 // ---------------------------------------------------------------- Philox4x64-10
@@ -73,33 +95,47 @@ __device__ inline U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
     return c;
 }
 
+// One pair of elements per thread.  Transcendentals are the hardware's: v_log_f32 (log2),
+// v_exp_f32 (2^x), v_sin_f32 / v_cos_f32 (argument in turns), v_rcp_f32.
+__device__ inline float noisy_value(float g, uint64_t w0, uint64_t w1, float M, float inv_M_log2e, float I0,
+                                    float sd_e) {
+    const float u1 = (float)((w0 >> 40) + 1) * 5.9604644775390625e-8f;     // (0, 1]
+    const float u2 = (float)(w1 >> 40) * 5.9604644775390625e-8f;           // [0, 1)
+    const float rho = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));   // sqrt(-2 ln u1)
+    const float z1 = rho * __builtin_amdgcn_cosf(u2), z2 = rho * __builtin_amdgcn_sinf(u2);
+    const float lam = I0 * __builtin_amdgcn_exp2f(-g * inv_M_log2e);
+    float counts = fmaf(sqrtf(lam), z1, lam) + sd_e * z2;
+    counts = fmaxf(counts, 1.0f);
+    return M * 0.69314718055994531f * __builtin_amdgcn_logf(I0 * __builtin_amdgcn_rcpf(counts));
+}
+
 __global__ __launch_bounds__(kThreads) void k_noise(const float *__restrict__ in, float *__restrict__ out,
                                                     unsigned long long n, const float *__restrict__ d_max,
                                                     float I0, float sd_e, uint64_t seed) {
-    const unsigned long long e = (unsigned long long)blockIdx.x * kThreads + threadIdx.x;
+    const unsigned long long pr = (unsigned long long)blockIdx.x * kThreads + threadIdx.x;
+    const unsigned long long e = 2 * pr;
     if (e >= n) return;
     const float M = *d_max;
+    const float inv_M_log2e = 1.4426950408889634f / M;
     U64x4 ctr;
-    ctr.v[0] = e;
+    ctr.v[0] = pr;
     ctr.v[1] = 0;
     ctr.v[2] = 0;
     ctr.v[3] = 0;
     const U64x4 x = philox4x64_10(ctr, seed, 0);
-    // 24-bit uniforms: u1 in (0, 1], u2 in [0, 1)
-    const float u1 = (float)((x.v[0] >> 40) + 1) * 5.9604644775390625e-8f;
-    const float u2 = (float)(x.v[1] >> 40) * 5.9604644775390625e-8f;
-    const float rho = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincosf(6.28318530717958647692f * u2, &s, &c);
-    const float z1 = rho * c, z2 = rho * s;
-    const float lam = I0 * expf(-in[e] / M);
-    float counts = fmaf(sqrtf(lam), z1, lam) + sd_e * z2;
-    counts = fmaxf(counts, 1.0f);
-    out[e] = M * logf(I0 / counts);
+    if (e + 1 < n && ((uintptr_t)(in + e) & 7) == 0 && ((uintptr_t)(out + e) & 7) == 0) {
+        const float2 g = *reinterpret_cast<const float2 *>(in + e);
+        *reinterpret_cast<float2 *>(out + e) =
+            make_float2(noisy_value(g.x, x.v[0], x.v[1], M, inv_M_log2e, I0, sd_e),
+                        noisy_value(g.y, x.v[2], x.v[3], M, inv_M_log2e, I0, sd_e));
+    } else {
+        out[e] = noisy_value(in[e], x.v[0], x.v[1], M, inv_M_log2e, I0, sd_e);
+        if (e + 1 < n) out[e + 1] = noisy_value(in[e + 1], x.v[2], x.v[3], M, inv_M_log2e, I0, sd_e);
+    }
 }
 
 // ---------------------------------------------------------------- reductions
-constexpr int kRedBlocks = 1024;     // partial sums per reduction (scratch of 8 doubles each)
+constexpr int kRedBlocks = 4096;     // partials per reduction (5 doubles each in scratch)
 
 __device__ inline double block_sum(double v, double *sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -123,9 +159,18 @@ __global__ __launch_bounds__(kThreads) void k_max_partial(const float *__restric
                                                           float *__restrict__ part) {
     __shared__ float sh[4];
     float m = -INFINITY;
-    for (unsigned long long i = (unsigned long long)blockIdx.x * kThreads + threadIdx.x; i < n;
-         i += (unsigned long long)gridDim.x * kThreads)
-        m = fmaxf(m, x[i]);
+    const unsigned long long stride = (unsigned long long)gridDim.x * kThreads;
+    const unsigned long long t0 = (unsigned long long)blockIdx.x * kThreads + threadIdx.x;
+    if (((uintptr_t)x & 15) == 0) {                 // 16-byte loads, then the tail
+        const unsigned long long n4 = n / 4;
+        for (unsigned long long q = t0; q < n4; q += stride) {
+            const float4 v = reinterpret_cast<const float4 *>(x)[q];
+            m = fmaxf(m, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+        }
+        for (unsigned long long i = n4 * 4 + t0; i < n; i += stride) m = fmaxf(m, x[i]);
+    } else {
+        for (unsigned long long i = t0; i < n; i += stride) m = fmaxf(m, x[i]);
+    }
     m = block_max(m, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
@@ -234,10 +279,12 @@ uint64_t data_scratch_bytes() { return (uint64_t)kRedBlocks * 5 * sizeof(double)
 hipError_t launch_upsample(const float *sp, float *full, long long lines, int cols, int ns, int step,
                            hipStream_t s) {
     if (lines <= 0 || cols <= 0) return hipSuccess;
-    const unsigned gy = (unsigned)(lines < 65535 ? lines : 65535);
-    const unsigned gz = (unsigned)((lines + gy - 1) / gy);
-    hipLaunchKernelGGL(k_upsample, dim3((cols + kThreads - 1) / kThreads, gy, gz), dim3(kThreads), 0, s,
-                       sp, full, lines, cols, ns, step);
+    const unsigned long long slots = ((unsigned long long)cols + 3) / 4;
+    if ((unsigned long long)lines * slots >= (1ull << 32)) return hipErrorInvalidValue;
+    const unsigned long long q = ((unsigned long long)lines * slots + kThreads - 1) / kThreads;
+    const unsigned blocks = (unsigned)(q > 16384 ? 16384 : q);
+    hipLaunchKernelGGL(k_upsample, dim3(blocks), dim3(kThreads), 0, s, sp, full, (unsigned)lines, cols, ns,
+                       step);
     return hipGetLastError();
 }
 
@@ -252,7 +299,8 @@ hipError_t launch_max(const float *x, unsigned long long n, float *out, void *sc
 hipError_t launch_noise(const float *in, float *out, unsigned long long n, const float *d_max, float I0,
                         float sd_e, uint64_t seed, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_noise, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+    const unsigned long long pairs = (n + 1) / 2;
+    hipLaunchKernelGGL(k_noise, dim3((unsigned)((pairs + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                        in, out, n, d_max, I0, sd_e, seed);
     return hipGetLastError();
 }

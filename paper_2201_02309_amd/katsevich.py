@@ -385,12 +385,12 @@ def sparse_upsample(sparse, cols: int, step: int = 4, out=None):
     return out
 
 
-def max_value(x, scratch=None):
+def max_value(x, scratch=None, out=None):
     """katsevich_max: device float32 tensor [1] holding max(x)."""
     import torch
     _f32(x, "x")
     scratch = _data_scratch(x.device) if scratch is None else scratch
-    out = torch.empty(1, dtype=torch.float32, device=x.device)
+    out = torch.empty(1, dtype=torch.float32, device=x.device) if out is None else out
     lib = load_library()
     _check(lib, lib.katsevich_max(c_void_p(x.data_ptr()), c_uint64(x.numel()), c_void_p(out.data_ptr()),
                                   c_void_p(scratch.data_ptr()), c_uint64(scratch.numel()),
