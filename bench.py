@@ -182,6 +182,94 @@ def data_path_bench(sino, vol, ref_vol, reps=5):
     return out
 
 
+def network_bench(steps=5, warmup=2):
+    """One training step (batch 1, forward + backward + Adam, Sec. III-B) of the dual-domain
+    network on one pitch of the paper's p = 7 pi workload: window sinogram of the 627 x 16
+    detector -> 512 x 512 x 10 slices.  The sample is the sparse (every 4th column) and noisy
+    input of Sec. III-C; labels are the noise-free window sinogram and the phantom."""
+    import numpy as np
+    import torch
+
+    import paper_2201_02309_amd as K
+    from paper_2201_02309_amd import network as N
+    from synth import configs, gpu_projector, phantom
+
+    dev = torch.device("cuda", 0)
+    wl = configs.network_pitch()
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    gw, _ = N.pitch_window_geometry(geom, gr)
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    g_gt = gpu_projector.project(ph, gw, device=dev)
+    g_in = K.add_noise(K.sparse_upsample(g_gt[..., ::4].contiguous(), gw["det_cols"], 4), 1e5, 0.5, 11)
+    z = gr["z_first"] + np.arange(gr["nz"]) * gr["dz"]
+    y = gr["y_first"] + np.arange(gr["ny"]) * gr["dy"]
+    x = gr["x_first"] + np.arange(gr["nx"]) * gr["dx"]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    f_gt = torch.from_numpy(phantom.density(ph, np.stack([X, Y, Z], -1)).astype(np.float32)).to(dev)
+    plan = K.Plan(gw, gr, device=0)
+    torch.manual_seed(0)
+    net = N.DualDomainNet(plan).to(dev)
+    opt = torch.optim.Adam(net.parameters(), lr=1e-3)
+    g_in, g_gt, f_gt = g_in[None], g_gt[None], f_gt[None]
+
+    # MIOpen compiles every convolution configuration on its first use (seconds to tens of
+    # seconds each): warm the distinct ones up one by one, reporting each
+    for name, sub, shape in (("sinogram", net.sino_net, tuple(g_in.shape[1:])),
+                             ("image", net.image_net, tuple(f_gt.shape[1:]))):
+        for label, conv, cin in (("first", sub.convs[0], 1), ("middle", sub.convs[1], 16),
+                                 ("last", sub.out, 16)):
+            x = torch.randn((1, cin) + shape, device=dev, requires_grad=True)
+            conv(x).sum().backward()
+            torch.cuda.synchronize()
+            print(f"[bench] network: {name} subnetwork, {label} convolution compiled",
+                  file=sys.stderr, flush=True)
+    opt.zero_grad(set_to_none=True)
+
+    def step():
+        opt.zero_grad(set_to_none=True)
+        gs, f = net(g_in)
+        L = N.loss(gs, f, g_gt, f_gt)
+        L.backward()
+        opt.step()
+        return L
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] network warm-up step {i + 1}/{warmup}", file=sys.stderr, flush=True)
+    losses = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        losses.append(step())
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / steps
+    # the Katsevich layer alone on the same plan: forward and adjoint
+    gsino = g_in[0].contiguous()
+    vol = K.recon(plan, gsino)
+    gvol = torch.randn_like(vol)
+    K.recon_backward(plan, gvol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        K.recon(plan, gsino, out=vol)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 200
+    t0 = time.perf_counter()
+    for _ in range(5):
+        K.recon_backward(plan, gvol)
+    torch.cuda.synchronize()
+    bwd_ms = (time.perf_counter() - t0) * 200
+    out = {"workload": f"one pitch of the p = 7 pi network workload: window sinogram "
+                       f"{tuple(g_in.shape[1:])}, slices {tuple(f_gt.shape[1:])}, batch 1, "
+                       f"16-channel 7-block subnetworks, Adam lr 1e-3",
+           "step_s": round(step_s, 4), "layer_forward_ms": round(fwd_ms, 3),
+           "layer_adjoint_ms": round(bwd_ms, 3),
+           "loss_first_last": [round(float(losses[0]), 3), round(float(losses[-1]), 3)],
+           "paper_step_s_other_hardware": "5-6 (RTX A6000, TensorFlow 2.5)"}
+    plan.close()
+    return out
+
+
 def _measured_traffic():
     """HBM bytes per backprojection launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (scaled by a plain-copy calibration), or None when the kernel or
@@ -205,6 +293,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--network", action="store_true",
+                    help="also time a training step of the dual-domain network (MIOpen compiles "
+                         "its convolutions first: a few minutes on a fresh machine)")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the serving comparison (0 skips it)")
     ap.add_argument("--bp-slices", type=int, default=0,
@@ -348,6 +439,8 @@ def main():
     K.recon(plan, K.add_noise(sino, 1e5, 0.5, 3), out=vol, ws=ws)
     out["data_path"] = data_path_bench(sino, vol, ref_vol)
     del ref_vol
+    if args.network:
+        out["network"] = network_bench()
     if args.serve_requests > 0:
         gF = ws = None
         plan.release_workspace()

@@ -702,15 +702,40 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
     }
 
     {
+        // Largest box a workgroup can stage: a workgroup only walks the views of its hull,
+        // the union of the PI windows (pitch-relative [nf, nl]) of the voxels of its tile and
+        // slice run that lie in the field of view; the kernels' own hull is a subset (it
+        // also drops voxels whose window leaves the scan), so tiles and views outside these
+        // hulls never touch their boxes.
         const BpBox *bx = reinterpret_cast<const BpBox *>(img + L.boxes);
-        const size_t nb = (size_t)P.bp_runs * P.bp_tiles_y * P.bp_tiles_x * P.W;
-        int mr = 0, mc = 0;
-        for (size_t i = 0; i < nb; ++i) {
-            mr = std::max(mr, (int)bx[i].nr);
-            mc = std::max(mc, (int)bx[i].nc);
-        }
-        P.bp_box_rows = mr;
-        P.bp_box_cols = mc;
+        const PiEntry *pe = reinterpret_cast<const PiEntry *>(img + L.pi);
+        const int tiles = P.bp_tiles_y * P.bp_tiles_x;
+        std::vector<int> tmr((size_t)P.bp_runs * tiles, 0), tmc((size_t)P.bp_runs * tiles, 0);
+        parallel_for(P.bp_runs * tiles, threads_for(opts), [&](int rt) {
+            const int run = rt / tiles, t = rt % tiles;
+            const int tx = t % P.bp_tiles_x, ty = t / P.bp_tiles_x;
+            int hlo = INT32_MAX, hhi = INT32_MIN;
+            const int j1 = std::min(P.n_tab, (run + 1) * P.bp_kz);
+            for (int j = run * P.bp_kz; j < j1; ++j)
+                for (int iy = ty * kBpTile; iy < std::min(gr.ny, (ty + 1) * kBpTile); ++iy)
+                    for (int ix = tx * kBpTile; ix < std::min(gr.nx, (tx + 1) * kBpTile); ++ix) {
+                        const PiEntry &q = pe[((size_t)j * gr.ny + iy) * gr.nx + ix];
+                        if (q.nf <= q.nl) {
+                            hlo = std::min(hlo, q.nf);
+                            hhi = std::max(hhi, q.nl);
+                        }
+                    }
+            int mr = 0, mc = 0;
+            for (int m = std::max(hlo, 0); m <= std::min(hhi, P.W - 1); ++m) {
+                const BpBox &b = bx[(size_t)rt * P.W + m];
+                mr = std::max(mr, (int)b.nr);
+                mc = std::max(mc, (int)b.nc);
+            }
+            tmr[(size_t)rt] = mr;
+            tmc[(size_t)rt] = mc;
+        });
+        P.bp_box_rows = *std::max_element(tmr.begin(), tmr.end());
+        P.bp_box_cols = *std::max_element(tmc.begin(), tmc.end());
     }
 
     // ------------------------------------------------------------------ workspace sizes

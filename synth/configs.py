@@ -192,6 +192,34 @@ def tiny(nxy=24, nz=16, cols=48, rows=8, views_per_turn=72, turns=3, feed=24.0,
         seed=seed)
 
 
+def network_pitch(nxy=512, dxy=1.0, cols=627, rows=16, views_per_turn=360, turns=4, h=3.5,
+                  slices=10, seed=3001) -> Workload:
+    """One pitch of the network workload of Sec. III-C at p = 7 pi (h = 3.5 mm/rad): R = 595,
+    D = 1085.6, a curved detector of 627 columns at 0.0625 deg with the quarter-column offset,
+    16 rows covering the Tam-Danielsson window + 10 %, 360 views per turn; a 512 x 512 grid
+    at 1 mm in-plane and the pitch's 10 slices at 2 pi h / 10 (the paper's 11 z positions
+    from 0 to 2 pi h include both ends; 10 of them repeat every pitch).  The field of view
+    (radius R sin(alpha_m) ~ 199 mm) leaves the grid's corners out.  Seeded ellipsoids
+    inside the field of view."""
+    R, D = 595.0, 1085.6
+    feed = 2.0 * math.pi * h
+    dalpha = math.pi / 2880.0                          # 0.0625 degree
+    alpha_m = (0.5 * (cols - 1) + 0.25) * dalpha
+    w_td = D * h / R * (0.5 * math.pi + alpha_m) / math.cos(alpha_m)
+    dw = 2.0 * 1.1 * w_td / (rows - 1)
+    geom = Geometry(R=R, D=D, feed_per_turn=feed, views_per_turn=views_per_turn,
+                    n_views=views_per_turn * turns, det_cols=cols, det_rows=rows,
+                    dalpha=dalpha, dw=dw, col_offset=0.25)
+    grid = centred_grid(geom, nxy, nxy, slices, dxy, feed / slices)
+    r_fov = R * math.sin(alpha_m - 0.25 * dalpha) * 0.9
+    ph = {"kind": "ellipsoids", "n": 10, "centre_radius": 0.45 * r_fov,
+          "semi_axes": (0.06 * r_fov, 0.35 * r_fov), "density": (0.1, 1.0),
+          "bound_radius": 0.95 * r_fov, "inserts": 20, "insert_radius": (2.0, 6.0),
+          "insert_density": 0.02}
+    return Workload(name=f"network-pitch-{nxy}^2x{slices}", geom=geom, grid=grid, phantom=ph,
+                    seed=seed)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
 
 

@@ -1,0 +1,98 @@
+"""The dual-domain network of Sec. III around the library's reconstruction layer: one pitch's
+window sinogram through the sinogram subnetwork, the Katsevich layer and the image
+subnetwork; the training loss of eq. loss and its gradient through the layer."""
+import numpy as np
+import pytest
+
+from synth import configs, phantom
+
+torch = pytest.importorskip("torch")
+K = pytest.importorskip("paper_2201_02309_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def sample():
+    from paper_2201_02309_amd import network as N
+    dev = _dev()
+    wl = configs.tiny(nxy=16, nz=12, cols=48, rows=8, views_per_turn=72, turns=4, feed=24.0,
+                      dxy=2.0, slices_per_pitch=12)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    gw, a = N.pitch_window_geometry(geom, gr)
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    g_gt = torch.from_numpy(phantom.project(ph, gw).astype(np.float32)).to(dev)
+    sp = g_gt[..., ::4].contiguous()
+    g_in = K.add_noise(K.sparse_upsample(sp, gw["det_cols"], 4), 1e5, 0.5, seed=5)
+    z = gr["z_first"] + np.arange(gr["nz"]) * gr["dz"]
+    y = gr["y_first"] + np.arange(gr["ny"]) * gr["dy"]
+    x = gr["x_first"] + np.arange(gr["nx"]) * gr["dx"]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    f_gt = torch.from_numpy(phantom.density(ph, np.stack([X, Y, Z], -1)).astype(np.float32)).to(dev)
+    plan = K.Plan(gw, gr, device=0)
+    return plan, g_in[None], g_gt[None], f_gt[None], gw, a
+
+
+def test_window_plan_reconstructs_like_the_whole_scan(sample):
+    """The pitch-window plan gives the same slices as the plan of the whole scan."""
+    dev = _dev()
+    plan, _, g_gt, _, gw, a = sample
+    wl = configs.tiny(nxy=16, nz=12, cols=48, rows=8, views_per_turn=72, turns=4, feed=24.0,
+                      dxy=2.0, slices_per_pitch=12)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    full = torch.from_numpy(phantom.project(ph, geom).astype(np.float32)).to(dev)
+    ref = K.recon(K.Plan(geom, gr, device=0), full)
+    got = K.recon(plan, full[a:a + gw["n_views"]].contiguous())
+    rel = float((got - ref).norm() / ref.norm())
+    print(f"[network] window plan vs whole-scan plan: rel-L2 {rel:.3e}", flush=True)
+    assert rel <= 1e-6
+
+
+def test_training_step_and_gradient_through_the_layer(sample):
+    from paper_2201_02309_amd import network as N
+    plan, g_in, g_gt, f_gt, _, _ = sample
+    torch.manual_seed(0)
+    net = N.DualDomainNet(plan).to(g_in.device)
+    gs, f = net(g_in)
+    assert gs.shape == g_in.shape and f.shape == f_gt.shape
+    L = N.loss(gs, f, g_gt, f_gt)
+    L.backward()
+    assert net.sino_net.convs[0].weight.grad.abs().sum() > 0
+    assert net.image_net.out.weight.grad.abs().sum() > 0
+    # the sinogram subnetwork's output bias reaches the image only through the layer: its
+    # gradient against a central difference of the loss (float64 sums of float32 tensors)
+    b = net.sino_net.out.bias
+    grad = float(b.grad[0])
+
+    def loss_at(v):
+        with torch.no_grad():
+            b.fill_(v)
+            gs, f = net(g_in)
+            return float(((g_gt - gs).double() ** 2).sum() + ((f_gt - f).double() ** 2).sum())
+    b0 = float(b.detach()[0])
+    eps = 1e-2
+    fd = (loss_at(b0 + eps) - loss_at(b0 - eps)) / (2 * eps)
+    with torch.no_grad():
+        b.fill_(b0)
+    print(f"[network] d loss / d sino-net output bias: autograd {grad:.6g}, central difference "
+          f"{fd:.6g}", flush=True)
+    assert abs(grad - fd) <= 2e-3 * abs(fd)
+    # a few Adam steps (Sec. III-B, lr 1e-3) lower the loss on this sample
+    opt = torch.optim.Adam(net.parameters(), lr=1e-3)
+    first = None
+    for _ in range(8):
+        opt.zero_grad()
+        gs, f = net(g_in)
+        L = N.loss(gs, f, g_gt, f_gt)
+        L.backward()
+        opt.step()
+        first = float(L) if first is None else first
+    print(f"[network] loss {first:.5g} -> {float(L):.5g} over 8 Adam steps", flush=True)
+    assert float(L) < first
