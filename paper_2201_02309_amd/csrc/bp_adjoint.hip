@@ -182,22 +182,36 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         for (int g = 0; g < NG; ++g) {
             if (!(word & (1u << g))) continue;
             const bool full = word & (1u << (kFull + g));
+            // slices in pairs of registers (p, p+1): their row weights are summed in
+            // registers where the two slices share detector rows (row step d = 0 or 1),
+            // then each non-zero row takes two atomics (columns c0, c0+1)
+            auto emit = [&](int row, float v) {
+                if (v != 0.0f) {
+                    const float v1 = v * tc;
+                    double *cell = bx + row * kLPT;
+                    atomicAdd(cell, (double)(v - v1));
+                    atomicAdd(cell + 1, (double)v1);
+                }
+            };
 #pragma unroll
-            for (int s = 0; s < kKG; ++s) {
-                const int r = g * kKG + s;                  // register (slice sf[r])
-                float a = vinv * fb[r];
-                if (!full) a *= med3(fminf(mf - A[r], B[r] - mf), 0.0f, 1.0f);
-                if (a != 0.0f) {
-                    const float rr = med3(fmaf(sf[r], st, rb), 0.0f, rmax);
-                    const int r0 = (int)rr;
-                    const float tr = __builtin_amdgcn_fractf(rr);
-                    const float a1 = a * tr, a0 = a - a1;          // rows r0, r0 + 1
-                    const float a01 = a0 * tc, a11 = a1 * tc;        // column c0 + 1
-                    double *cell = bx + r0 * kLPT;
-                    atomicAdd(cell, (double)(a0 - a01));
-                    atomicAdd(cell + 1, (double)a01);
-                    atomicAdd(cell + kLPT, (double)(a1 - a11));
-                    atomicAdd(cell + kLPT + 1, (double)a11);
+            for (int s = 0; s < kKG; s += 2) {
+                const int p = g * kKG + s, q = p + 1;         // registers (slices sf[p], sf[q])
+                float ap = vinv * fb[p], aq = vinv * fb[q];
+                if (!full) {
+                    ap *= med3(fminf(mf - A[p], B[p] - mf), 0.0f, 1.0f);
+                    aq *= med3(fminf(mf - A[q], B[q] - mf), 0.0f, 1.0f);
+                }
+                if (ap != 0.0f || aq != 0.0f) {
+                    const float rp = med3(fmaf(sf[p], st, rb), 0.0f, rmax);
+                    const float rq = med3(fmaf(sf[q], st, rb), 0.0f, rmax);
+                    const int Rp = (int)rp, Rq = (int)rq;
+                    const float p1 = ap * __builtin_amdgcn_fractf(rp), p0 = ap - p1;   // rows Rp, Rp+1
+                    const float q1 = aq * __builtin_amdgcn_fractf(rq), q0 = aq - q1;   // rows Rq, Rq+1
+                    const int d = Rq - Rp;
+                    emit(Rp, d == 0 ? p0 + q0 : p0);
+                    emit(Rp + 1, d == 0 ? p1 + q1 : (d == 1 ? p1 + q0 : p1));
+                    emit(Rq + 1, d == 0 ? 0.0f : q1);
+                    emit(Rq, (d == 0 || d == 1) ? 0.0f : q0);
                 }
             }
         }
