@@ -178,42 +178,43 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         unsigned word = (1u << NG) - 1u;
         if (use_words) word = __builtin_amdgcn_readfirstlane(words[wave][m - mlo]);
         double *bx = box[buf] + c0;
+        // the view's active slices in register order: each slice adds its row weights to
+        // two pending rows (R, R+1) kept in registers; a row's two atomics (columns c0,
+        // c0+1) are issued once the walk has moved past it, so slices that share detector
+        // rows (row steps of 0 or 1) meet in registers first
+        auto emit = [&](int row, float v) {
+            if (v != 0.0f) {
+                const float v1 = v * tc;
+                double *cell = bx + row * kLPT;
+                atomicAdd(cell, (double)(v - v1));
+                atomicAdd(cell + 1, (double)v1);
+            }
+        };
+        int R = -1;                                           // -1: nothing pending yet
+        float P = 0.0f, Q = 0.0f;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (!(word & (1u << g))) continue;
             const bool full = word & (1u << (kFull + g));
-            // slices in pairs of registers (p, p+1): their row weights are summed in
-            // registers where the two slices share detector rows (row step d = 0 or 1),
-            // then each non-zero row takes two atomics (columns c0, c0+1)
-            auto emit = [&](int row, float v) {
-                if (v != 0.0f) {
-                    const float v1 = v * tc;
-                    double *cell = bx + row * kLPT;
-                    atomicAdd(cell, (double)(v - v1));
-                    atomicAdd(cell + 1, (double)v1);
-                }
-            };
 #pragma unroll
-            for (int s = 0; s < kKG; s += 2) {
-                const int p = g * kKG + s, q = p + 1;         // registers (slices sf[p], sf[q])
-                float ap = vinv * fb[p], aq = vinv * fb[q];
-                if (!full) {
-                    ap *= med3(fminf(mf - A[p], B[p] - mf), 0.0f, 1.0f);
-                    aq *= med3(fminf(mf - A[q], B[q] - mf), 0.0f, 1.0f);
-                }
-                if (ap != 0.0f || aq != 0.0f) {
-                    const float rp = med3(fmaf(sf[p], st, rb), 0.0f, rmax);
-                    const float rq = med3(fmaf(sf[q], st, rb), 0.0f, rmax);
-                    const int Rp = (int)rp, Rq = (int)rq;
-                    const float p1 = ap * __builtin_amdgcn_fractf(rp), p0 = ap - p1;   // rows Rp, Rp+1
-                    const float q1 = aq * __builtin_amdgcn_fractf(rq), q0 = aq - q1;   // rows Rq, Rq+1
-                    const int d = Rq - Rp;
-                    emit(Rp, d == 0 ? p0 + q0 : p0);
-                    emit(Rp + 1, d == 0 ? p1 + q1 : (d == 1 ? p1 + q0 : p1));
-                    emit(Rq + 1, d == 0 ? 0.0f : q1);
-                    emit(Rq, (d == 0 || d == 1) ? 0.0f : q0);
-                }
+            for (int s = 0; s < kKG; ++s) {
+                const int r = g * kKG + s;                    // register (slice sf[r])
+                float a = vinv * fb[r];
+                if (!full) a *= med3(fminf(mf - A[r], B[r] - mf), 0.0f, 1.0f);
+                const float rr = med3(fmaf(sf[r], st, rb), 0.0f, rmax);
+                const int Rk = (int)rr;
+                const float a1 = a * __builtin_amdgcn_fractf(rr), a0 = a - a1;   // rows Rk, Rk+1
+                const bool same = Rk == R, next = Rk == R + 1;
+                if (!same && R >= 0) emit(R, P);
+                if (!same && !next && R >= 0) emit(R + 1, Q);
+                P = same ? P + a0 : (next ? Q + a0 : a0);
+                Q = same ? Q + a1 : a1;
+                R = Rk;
             }
+        }
+        if (R >= 0) {
+            emit(R, P);
+            emit(R + 1, Q);
         }
         if (m > mlo) flush(m - 1, prev_b, buf ^ 1);
         prev_b = b;
