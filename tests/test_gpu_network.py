@@ -93,6 +93,7 @@ def test_training_step_and_gradient_through_the_layer(sample):
         L = N.loss(gs, f, g_gt, f_gt)
         L.backward()
         opt.step()
-        first = float(L) if first is None else first
-    print(f"[network] loss {first:.5g} -> {float(L):.5g} over 8 Adam steps", flush=True)
-    assert float(L) < first
+        first = float(L.detach()) if first is None else first
+    last = float(L.detach())
+    print(f"[network] loss {first:.5g} -> {last:.5g} over 8 Adam steps", flush=True)
+    assert last < first
