@@ -231,7 +231,7 @@ def network_bench(steps=5, warmup=2):
         L = N.loss(gs, f, g_gt, f_gt)
         L.backward()
         opt.step()
-        return L
+        return L.detach()
 
     for i in range(warmup):
         step()
