@@ -82,6 +82,30 @@ def sparse_upsample(gs, cols, step=4):
     return out.reshape(gs.shape[:-1] + (cols,))
 
 
+def normals_at(idx, seed):
+    """(z1, z2) of the given element indices (any order, any size of the full array)."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    ctr = np.zeros((idx.size, 4), np.uint64)
+    ctr[:, 0] = idx >> np.uint64(1)
+    x = philox4x64_10(ctr, (seed, 0))
+    odd = (idx & np.uint64(1)).astype(bool)
+    first = np.where(odd, x[:, 2], x[:, 0])
+    second = np.where(odd, x[:, 3], x[:, 1])
+    u1 = ((first >> np.uint64(40)).astype(np.float64) + 1.0) * 2.0 ** -24
+    u2 = (second >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+    rho = np.sqrt(-2.0 * np.log(u1))
+    return rho * np.cos(2.0 * np.pi * u2), rho * np.sin(2.0 * np.pi * u2)
+
+
+def add_noise_at(g_values, idx, M, I0=1e5, var=0.5, seed=0):
+    """The noisy values of the elements idx whose data are g_values (same rule as add_noise)."""
+    g = np.asarray(g_values, np.float64)
+    z1, z2 = normals_at(idx, seed)
+    lam = I0 * np.exp(-g / M)
+    counts = np.maximum(lam + np.sqrt(lam) * z1 + np.sqrt(var) * z2, 1.0)
+    return M * np.log(I0 / counts)
+
+
 def normals(n, seed):
     """(z1, z2) of elements 0 .. n-1."""
     nb = (n + 1) // 2

@@ -90,3 +90,13 @@ def test_rmse_ssim_identities():
     e = rng.normal(size=x.shape)
     s = [D.ssim(x + a * e, x) for a in (0.1, 0.5, 1.0)]
     assert 1.0 > s[0] > s[1] > s[2]
+
+
+def test_normals_at_equals_the_sequence():
+    z1, z2 = D.normals(1001, seed=8)
+    idx = np.array([0, 1, 2, 999, 1000, 513, 514])
+    a1, a2 = D.normals_at(idx, seed=8)
+    assert np.array_equal(a1, z1[idx]) and np.array_equal(a2, z2[idx])
+    g = np.linspace(0, 40, 1001)
+    full = D.add_noise(g, M=50.0, seed=8)
+    assert np.array_equal(D.add_noise_at(g[idx], idx, 50.0, seed=8), full[idx])

@@ -109,3 +109,48 @@ def test_sparse_noisy_chain_parity(case):
           f"ssim {r_ssim:.6g}", flush=True)
     assert 0 < m[0] and m[1] < 1
     assert abs(m[0] - r_rmse) <= 1e-3 * r_rmse and abs(m[1] - r_ssim) <= 1e-4
+
+
+def test_data_path_full_size_sampled():
+    """The bench's configuration: the whole clinical sinogram (6960 x 64 x 736, 3.3e8
+    samples, 64-bit element indices in the noise counter) sparse-sampled, upsampled and
+    noised on the GPU; sampled lines and elements against the oracle, and the metrics of
+    two full 512^2 x 128 volumes against float64 NumPy."""
+    from synth import gpu_projector
+    dev = _dev()
+    wl = configs.config2()
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    print("[case] clinical sinogram for the data path", flush=True)
+    sino = gpu_projector.project(ph, geom, device=dev)
+    cols = sino.shape[-1]
+    sp = sino[..., ::4].contiguous()
+    up = K.sparse_upsample(sp, cols, 4)
+    d_max = K.max_value(up)
+    noisy = K.add_noise(up, 1e5, 0.5, seed=21, d_max=d_max)
+    rng = np.random.default_rng(12)
+    lines = rng.integers(0, sino.shape[0] * sino.shape[1], 300)
+    sp_l = sp.reshape(-1, sp.shape[-1])[torch.from_numpy(lines).to(dev)].cpu().numpy()
+    up_l = up.reshape(-1, cols)[torch.from_numpy(lines).to(dev)].cpu().numpy()
+    ref_l = D.sparse_upsample(sp_l.astype(np.float64), cols, 4)
+    e_up = np.abs(up_l - ref_l).max()
+    M = float(d_max.item())
+    assert M == float(up.max().item())
+    idx = np.concatenate([rng.integers(0, up.numel(), 20000),
+                          np.arange(up.numel() - 5, up.numel())])     # the last elements too
+    ti = torch.from_numpy(idx).to(dev)
+    g_s = up.reshape(-1)[ti].cpu().numpy().astype(np.float64)
+    n_s = noisy.reshape(-1)[ti].cpu().numpy().astype(np.float64)
+    ref_n = D.add_noise_at(g_s, idx, M, I0=1e5, var=0.5, seed=21)
+    rel_noise = np.linalg.norm((n_s - g_s) - (ref_n - g_s)) / np.linalg.norm(ref_n - g_s)
+    print(f"[parity] full-size upsample max-abs {e_up:.3e}; noise component rel-L2 "
+          f"{rel_noise:.3e} over {idx.size} elements (M {M:.2f})", flush=True)
+    assert e_up <= 2e-6 * np.abs(ref_l).max() and rel_noise <= 1e-4
+    a = torch.rand(gr["nz"], gr["ny"], gr["nx"], device=dev, generator=torch.Generator(dev).manual_seed(3))
+    b = (a + 0.05 * torch.randn(a.shape, device=dev, generator=torch.Generator(dev).manual_seed(4))).contiguous()
+    r = K.rmse_ssim(b, a).cpu().numpy()
+    an, bn = a.cpu().numpy(), b.cpu().numpy()
+    e_rmse, e_ssim = D.rmse(bn, an), D.ssim(bn, an)
+    print(f"[parity] full-volume metrics: rmse {r[0]:.12g} vs {e_rmse:.12g}, ssim {r[1]:.12g} vs "
+          f"{e_ssim:.12g}", flush=True)
+    assert abs(r[0] - e_rmse) <= 1e-9 * e_rmse and abs(r[1] - e_ssim) <= 1e-9
