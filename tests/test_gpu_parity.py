@@ -207,36 +207,36 @@ def test_wrong_shapes_are_rejected(case1, plan1):
 
 
 # ------------------------------------------------------------------ clinical config (sampled)
-def test_clinical_config_sampled_parity():
-    """512^2 x 128 clinical workload at full size, in the launch configuration the
-    benchmark times: the GPU volume at 300 random voxels (plus 24 near the z ends and the
-    FOV edge) against the oracle computed voxel by voxel from the same float32 sinogram."""
+def _sampled_parity(wl, name, n, z_ends, x_edges, half=False, seed=11):
+    """GPU volume of the whole workload at n random voxels plus voxels near the z ends and
+    the FOV edge, against the oracle computed voxel by voxel from the same float32
+    sinogram (filtering only the views the plan uses)."""
     dev = _dev()
     from synth import gpu_projector
-    wl = configs.config2()
     geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
-    print("[case] config2 sampled parity", flush=True)
-    plan = K.Plan(geom, gr, device=0)
+    print(f"[case] {name} sampled parity", flush=True)
+    plan = K.Plan(geom, gr, device=0, half_sample=half)
     a, b = plan.info["first_view"], plan.info["last_view"]
+    hi = b + 2 + (1 if half else 0)             # sinogram views a-1 .. hi-1 feed the filter
     sino_d = torch.zeros((geom["n_views"], geom["det_rows"], geom["det_cols"]),
                          dtype=torch.float32, device=dev)
-    gpu_projector.project(ph, geom, views=np.arange(a - 1, b + 2), out=sino_d[a - 1:b + 2])
+    gpu_projector.project(ph, geom, views=np.arange(a - 1, hi), out=sino_d[a - 1:hi])
     # the GPU projector against the closed form on the host, on a few views
-    chk = np.array([a - 1, (a + b) // 2, b + 1])
+    chk = np.array([a - 1, (a + b) // 2, hi - 1])
     host = phantom.project(ph, geom, views=chk)
     got = sino_d[torch.from_numpy(chk).to(dev)].cpu().numpy()
     assert np.abs(got - host).max() <= 1e-5 * np.abs(host).max()
     vol = K.recon(plan, sino_d).cpu().numpy()
     torch.cuda.synchronize()
-    sino = sino_d[a - 1:b + 2].cpu().numpy()
+    sino = sino_d[a - 1:hi].cpu().numpy()
     del sino_d
-    scan = O.Scan(geom)
-    rng = np.random.default_rng(11)
-    n = 300
-    iz = np.concatenate([rng.integers(0, gr["nz"], n), [0, 1, 76, 77, 126, 127] * 4])
+    scan = O.Scan(O.half_sample_geometry(geom) if half else geom)
+    rng = np.random.default_rng(seed)
+    ze = np.asarray(z_ends)
+    iz = np.concatenate([rng.integers(0, gr["nz"], n), np.tile(ze, 24 // len(ze))])
     iy = np.concatenate([rng.integers(0, gr["ny"], n), rng.integers(0, gr["ny"], 24)])
-    ix = np.concatenate([rng.integers(0, gr["nx"], n), np.tile([0, 511, 3, 508], 6)])
+    ix = np.concatenate([rng.integers(0, gr["nx"], n), np.tile(x_edges, 24 // len(x_edges))])
     valid = plan.export("valid").astype(bool)[iz, iy, ix]
     pit = O.Pitches(scan, gr)
     k, j = iz // pit.ns, iz % pit.ns
@@ -247,22 +247,44 @@ def test_clinical_config_sampled_parity():
     li, lo, nf, nl = O.pi_view_bounds(scan, Li, Lo)
     ref = np.zeros(len(iz))
     prog = lambda i, n: print(f"[oracle] filtering view {i} of {n}", flush=True)
-    gF = O.filter_views(scan, sino, O.FilterTables(scan), progress=prog)   # views a-1 .. b+1
+    gF = O.filter_views(scan, sino, O.FilterTables(scan), progress=prog, half=half)
     print("[oracle] backprojecting sampled voxels", flush=True)
     for kk in np.unique(k):
         m = (k == kk) & valid
-        s = kk * scan.Nv
-        ref[m] = O.backproject(scan, gF, a - 1, x[m], y[m], zj[m], li[m] + s, lo[m] + s,
-                               nf[m] + s, nl[m] + s, lam_shift=2 * math.pi * kk)
+        sh = kk * scan.Nv
+        ref[m] = O.backproject(scan, gF, a - 1, x[m], y[m], zj[m], li[m] + sh, lo[m] + sh,
+                               nf[m] + sh, nl[m] + sh, lam_shift=2 * math.pi * kk)
     got = vol[iz, iy, ix]
-    coarse = dict(gr, nx=128, ny=128, nz=32, dx=4 * gr["dx"], dy=4 * gr["dy"], dz=4 * gr["dz"])
+    coarse = dict(gr, nx=gr["nx"] // 4, ny=gr["ny"] // 4, nz=max(gr["nz"] // 4, 1),
+                  dx=4 * gr["dx"], dy=4 * gr["dy"], dz=4 * gr["dz"])
     peak = float(phantom.density(ph, _grid_points(coarse)).max())
     d = (got - ref)[valid]
     rel = float(np.linalg.norm(d) / np.linalg.norm(ref[valid]))
-    print(f"[parity] config2 sampled: rel-L2 {rel:.3e} max-abs {np.abs(d).max():.3e} "
+    print(f"[parity] {name} sampled: rel-L2 {rel:.3e} max-abs {np.abs(d).max():.3e} "
           f"({int(valid.sum())} valid of {len(iz)})", flush=True)
+    assert valid.sum() > n // 2
     assert np.all(got[~valid] == 0)
     assert rel <= REL_L2 and np.abs(d).max() <= MAX_ABS_OF_PEAK * peak
+
+
+def test_clinical_config_sampled_parity():
+    """512^2 x 128 clinical workload at full size, in the launch configuration the
+    benchmark times."""
+    _sampled_parity(configs.config2(), "config2", 300, [0, 1, 76, 77, 126, 127], [0, 511, 3, 508])
+
+
+def test_clinical_config_half_sample_sampled_parity():
+    """The same workload with the half-sample derivative."""
+    _sampled_parity(configs.config2(), "config2 half-sample", 200, [0, 1, 76, 77, 126, 127],
+                    [0, 511, 3, 508], half=True, seed=13)
+
+
+def test_sparse_detector_config_sampled_parity():
+    """Sparse-detector geometry (184 columns at 96 mm/turn, 256^2 x 64 grid): w_kappa turns
+    over inside the psi range and the footprint boxes exceed the LDS tile (the kernels'
+    HBM path)."""
+    _sampled_parity(configs.config3(), "config3", 300, [0, 1, 47, 48, 62, 63], [0, 255, 2, 253],
+                    seed=17)
 
 
 # ------------------------------------------------------------------ adjoint
