@@ -34,7 +34,9 @@ struct BpTShared {
     int red[8];
 };
 
-template <int KZ, bool P4>
+// FB: some box of the plan may exceed the LDS tile; those views scatter their taps
+// straight into g^F-bar with global atomics (the cells the forward's HBM path reads).
+template <int KZ, bool FB, bool P4>
 __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *__restrict__ gFbar,
                          int rows, int cols, long long first_view,
                          const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
@@ -63,7 +65,7 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     // register r of a lane holds slice (r + off) mod KZ: lanes of a wave that lie on one ray
     // then scatter slices of different z (different detector rows) in the same instruction
     const int off = ((tid & 15) + 4 * ((tid >> 4) & 3)) & (KZ - 1);
-    float A[KZ], B[KZ], fb[KZ], sf[KZ];
+    float A[KZ], B[KZ], fb[KZ];
     int wlo = INT_MAX, whi = INT_MIN;
     int g_alo[NG], g_ahi[NG], g_flo[NG], g_fhi[NG];
 #pragma unroll
@@ -73,7 +75,6 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         for (int s = 0; s < kKG; ++s) {
             const int r = g * kKG + s;                      // register
             const int jj = (r + off) & (KZ - 1);            // slice
-            sf[r] = (float)jj;
             A[r] = 3.0e38f;
             B[r] = -3.0e38f;
             fb[r] = 0.0f;
@@ -130,6 +131,7 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     const uint2 *__restrict__ boxes =
         box_tab + ((size_t)(run * p.tiles_y + byi) * p.tiles_x + bxi) * p.W;
     const size_t vstride = (size_t)rows * cols;
+    auto fits = [](const BpBox &b) { return !FB || (b.nr <= kLR && b.nc <= kLPT); };
     // flush of view m's box from buffer buf: lanes over 4 rows x 64 columns per pass
     auto flush = [&](int m, const BpBox &b, int buf) {
         double *bx = box[buf];
@@ -177,177 +179,106 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         const float mf = (float)m;
         unsigned word = (1u << NG) - 1u;
         if (use_words) word = __builtin_amdgcn_readfirstlane(words[wave][m - mlo]);
-        double *bx = box[buf] + c0;
         // the view's active slices in register order: each slice adds its row weights to
-        // two pending rows (R, R+1) kept in registers; a row's two atomics (columns c0,
-        // c0+1) are issued once the walk has moved past it, so slices that share detector
+        // two pending rows (R, R+1) kept in registers; a row's two taps (columns c0, c0+1)
+        // are scattered once the walk has moved past it, so slices that share detector
         // rows (row steps of 0 or 1) meet in registers first
-        auto emit = [&](int row, float v) {
-            if (v != 0.0f) {
-                const float v1 = v * tc;
-                double *cell = bx + row * kLPT;
-                atomicAdd(cell, (double)(v - v1));
-                atomicAdd(cell + 1, (double)v1);
+        auto walk = [&](auto emit) {
+            int R = -1;                                       // -1: nothing pending yet
+            float P = 0.0f, Q = 0.0f;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (!(word & (1u << g))) continue;
+                const bool full = word & (1u << (kFull + g));
+#pragma unroll
+                for (int s = 0; s < kKG; ++s) {
+                    const int r = g * kKG + s;                // register
+                    const float sl = (float)((r + off) & (KZ - 1));     // its slice
+                    float a = vinv * fb[r];
+                    if (!full) a *= med3(fminf(mf - A[r], B[r] - mf), 0.0f, 1.0f);
+                    const float rr = med3(fmaf(sl, st, rb), 0.0f, rmax);
+                    const int Rk = (int)rr;
+                    const float a1 = a * __builtin_amdgcn_fractf(rr), a0 = a - a1;   // rows Rk, Rk+1
+                    const bool same = Rk == R, next = Rk == R + 1;
+                    if (!same && R >= 0) emit(R, P);
+                    if (!same && !next && R >= 0) emit(R + 1, Q);
+                    P = same ? P + a0 : (next ? Q + a0 : a0);
+                    Q = same ? Q + a1 : a1;
+                    R = Rk;
+                }
+            }
+            if (R >= 0) {
+                emit(R, P);
+                emit(R + 1, Q);
             }
         };
-        int R = -1;                                           // -1: nothing pending yet
-        float P = 0.0f, Q = 0.0f;
-#pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            if (!(word & (1u << g))) continue;
-            const bool full = word & (1u << (kFull + g));
-#pragma unroll
-            for (int s = 0; s < kKG; ++s) {
-                const int r = g * kKG + s;                    // register (slice sf[r])
-                float a = vinv * fb[r];
-                if (!full) a *= med3(fminf(mf - A[r], B[r] - mf), 0.0f, 1.0f);
-                const float rr = med3(fmaf(sf[r], st, rb), 0.0f, rmax);
-                const int Rk = (int)rr;
-                const float a1 = a * __builtin_amdgcn_fractf(rr), a0 = a - a1;   // rows Rk, Rk+1
-                const bool same = Rk == R, next = Rk == R + 1;
-                if (!same && R >= 0) emit(R, P);
-                if (!same && !next && R >= 0) emit(R + 1, Q);
-                P = same ? P + a0 : (next ? Q + a0 : a0);
-                Q = same ? Q + a1 : a1;
-                R = Rk;
-            }
+        if (fits(b)) {
+            double *bx = box[buf] + c0;
+            walk([&](int row, float v) {
+                if (v != 0.0f) {
+                    const float v1 = v * tc;
+                    double *cell = bx + row * kLPT;
+                    atomicAdd(cell, (double)(v - v1));
+                    atomicAdd(cell + 1, (double)v1);
+                }
+            });
+        } else {
+            // rows and columns relative to the box, which is clipped to the zero-padded
+            // detector; cells of the padding are dropped (the forward reads zeros there)
+            float *img = gFbar + (size_t)(base + m - first_view) * vstride;
+            const int c = b.c0 + c0;
+            walk([&](int row, float v) {
+                const int rd = b.r0 + row;
+                if (v != 0.0f && (unsigned)rd < (unsigned)rows) {
+                    const float v1 = v * tc;
+                    float *q = img + (size_t)rd * cols;
+                    if ((unsigned)c < (unsigned)cols) atomicAdd(q + c, v - v1);
+                    if ((unsigned)(c + 1) < (unsigned)cols) atomicAdd(q + c + 1, v1);
+                }
+            });
         }
-        if (R >= 0) {
-            emit(R, P);
-            emit(R + 1, Q);
-        }
-        if (m > mlo) flush(m - 1, prev_b, buf ^ 1);
+        if (m > mlo && fits(prev_b)) flush(m - 1, prev_b, buf ^ 1);
         prev_b = b;
         __syncthreads();
     }
-    if (mlo <= mhi) flush(mhi, prev_b, (mhi - mlo) & 1);
+    if (mlo <= mhi && fits(prev_b)) flush(mhi, prev_b, (mhi - mlo) & 1);
 }
 
-template <int KZ, bool P4>
+template <int KZ, bool FB, bool P4>
 __global__ __launch_bounds__(kNT) void k_bpT_lds(BpArgs p, const float *__restrict__ fvol,
                                                  float *__restrict__ gFbar, int rows, int cols,
                                                  long long first_view,
                                                  const float4 *__restrict__ view_tab,
                                                  const uint2 *__restrict__ box_tab) {
     __shared__ BpTShared<KZ> S;
-    bpT_tile<KZ, P4>(p, fvol, gFbar, rows, cols, first_view, view_tab, box_tab, blockIdx.x,
-                     blockIdx.y, blockIdx.z, S);
+    bpT_tile<KZ, FB, P4>(p, fvol, gFbar, rows, cols, first_view, view_tab, box_tab, blockIdx.x,
+                         blockIdx.y, blockIdx.z, S);
 }
 
-// ---------------------------------------------------------------------------------
-// Adjoint of the backprojection (the transpose of the operator above, acting on an
-// unpadded g^F cotangent).
-// ---------------------------------------------------------------------------------
-constexpr int kTile = 8;          // 8 x 8 lanes per wave
-constexpr int kKZ = 8;            // slices per lane
-
-// Transpose: gFbar[n] += dlambda/(2 pi) c_n / v*_n * fbar(x) spread over the four bilinear
-// taps (global float atomics; the adjoint's only non-deterministic summation order).
 template <int KZ>
-__global__ __launch_bounds__(64) void k_backproject_T(KParams p, const float *__restrict__ gvol,
-                                                      float *__restrict__ gFbar, int runs_per_pitch) {
-    const int lane = threadIdx.x;
-    const int ix = blockIdx.x * kTile + (lane & (kTile - 1));
-    const int iy = blockIdx.y * kTile + (lane >> 3);
-    const int pitch = blockIdx.z / runs_per_pitch;
-    const int j0 = (blockIdx.z % runs_per_pitch) * KZ;
-    const int slices = min(p.ns, p.nz - pitch * p.ns);
-    const int nrun = min(KZ, slices - j0);
-    if (nrun <= 0) return;
-    const bool inxy = ix < p.nx && iy < p.ny;
-    const long long base = (long long)p.n_lo + (long long)pitch * p.Nv;
-    float A[KZ], B[KZ], g[KZ];
-    int mlo = INT_MAX, mhi = INT_MIN;
-    const int iz0 = pitch * p.ns + j0;
-#pragma unroll
-    for (int jj = 0; jj < KZ; ++jj) {
-        A[jj] = 3.0e38f;
-        B[jj] = -3.0e38f;
-        g[jj] = 0.0f;
-        if (inxy && jj < nrun) {
-            const PiEntry e = p.pi[((size_t)(j0 + jj) * p.ny + iy) * p.nx + ix];
-            const long long nf = base + e.nf, nl = base + e.nl;
-            if (e.nf <= e.nl && nf - 1 >= 0 && nl + 1 <= p.n_views - 1) {
-                A[jj] = e.li - 0.5f;
-                B[jj] = e.lo + 0.5f;
-                g[jj] = gvol[((size_t)(iz0 + jj) * p.ny + iy) * p.nx + ix] * p.scale;
-                mlo = min(mlo, e.nf);
-                mhi = max(mhi, e.nl);
-            }
-        }
-    }
-    mlo = __builtin_amdgcn_readfirstlane(wave_min(mlo));
-    mhi = __builtin_amdgcn_readfirstlane(wave_max(mhi));
-    const float x = fmaf((float)ix, p.dx, p.x_first);
-    const float y = fmaf((float)iy, p.dy, p.y_first);
-    const float zoff = (float)j0 * p.dz;
-    const size_t rc = (size_t)p.rows * p.cols;
-    for (int m = mlo; m <= mhi; ++m) {
-        const float4 vt = p.view[m];
-        const float u = fmaf(-x, vt.y, y * vt.x);
-        const float v = p.R - fmaf(x, vt.x, y * vt.y);
-        const float vinv = 1.0f / v;
-        const float rinv = rsqrtf(fmaf(u, u, v * v));
-        const float cc = fmaf(atan2f(u, v), p.inv_dalpha, p.col_c);
-        const float ccl = fminf(fmaxf(cc, -2.0f), (float)p.cols);
-        const float c0f = floorf(ccl);
-        const float tc = ccl - c0f;
-        const int c0 = (int)c0f;
-        const float q = p.D * rinv * p.inv_dw;
-        const float ez = vt.z + zoff;
-        float *img = gFbar + (size_t)(base + m - p.first_view) * rc;
-        const float mf = (float)m;
-#pragma unroll
-        for (int jj = 0; jj < KZ; ++jj) {
-            const float cw = fminf(fmaxf(fminf(mf - A[jj], B[jj] - mf), 0.0f), 1.0f);
-            const float amp = cw * vinv * g[jj];
-            if (amp == 0.0f) continue;
-            const float rr = fmaf(q, fmaf((float)jj, p.dz, ez), p.row_c);
-            const float rrl = fminf(fmaxf(rr, -2.0f), (float)p.rows);
-            const float r0f = floorf(rrl);
-            const float tr = rrl - r0f;
-            const int r0 = (int)r0f;
-            const float w00 = (1.0f - tr) * (1.0f - tc), w01 = (1.0f - tr) * tc;
-            const float w10 = tr * (1.0f - tc), w11 = tr * tc;
-            if ((unsigned)r0 < (unsigned)p.rows) {
-                if ((unsigned)c0 < (unsigned)p.cols) atomicAdd(img + r0 * p.cols + c0, amp * w00);
-                if ((unsigned)(c0 + 1) < (unsigned)p.cols) atomicAdd(img + r0 * p.cols + c0 + 1, amp * w01);
-            }
-            if ((unsigned)(r0 + 1) < (unsigned)p.rows) {
-                if ((unsigned)c0 < (unsigned)p.cols) atomicAdd(img + (r0 + 1) * p.cols + c0, amp * w10);
-                if ((unsigned)(c0 + 1) < (unsigned)p.cols)
-                    atomicAdd(img + (r0 + 1) * p.cols + c0 + 1, amp * w11);
-            }
-        }
+void launch_bpT(int cls, dim3 grid, hipStream_t s, const BpArgs &a, const float *gvol, float *gFbar,
+                int rows, int cols, long long first_view, const float4 *view, const uint2 *boxes) {
+    switch (cls) {      // bit 0: HBM path for boxes beyond the LDS tile, bit 1: short atan polynomial
+        case 0: hipLaunchKernelGGL((k_bpT_lds<KZ, false, false>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
+        case 1: hipLaunchKernelGGL((k_bpT_lds<KZ, true, false>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
+        case 2: hipLaunchKernelGGL((k_bpT_lds<KZ, false, true>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
+        default: hipLaunchKernelGGL((k_bpT_lds<KZ, true, true>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
     }
 }
 
 }  // namespace
 
 hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFbar, hipStream_t s) {
-    if (k.bp_all_fit) {
-        // tiled adjoint: LDS-accumulated boxes, one global atomic per cell and view
-        const dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
-        const BpArgs a = bp_args(k);
-        const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
-        const bool p4 = k.atan_deg >= 0 && k.atan_deg <= 4;
-#define KATS_BPT(KZ, P4) hipLaunchKernelGGL((k_bpT_lds<KZ, P4>), grid, dim3(kNT), 0, s, a, gvol, gFbar, \
-                                            k.rows, k.cols, k.first_view, k.view, boxes)
-        switch (k.bp_kz) {
-            case 8: if (p4) KATS_BPT(8, true); else KATS_BPT(8, false); break;
-            case 32: if (p4) KATS_BPT(32, true); else KATS_BPT(32, false); break;
-            default: if (p4) KATS_BPT(16, true); else KATS_BPT(16, false); break;
-        }
-#undef KATS_BPT
-        return hipGetLastError();
+    const dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
+    const BpArgs a = bp_args(k);
+    const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
+    const int cls = (k.bp_all_fit ? 0 : 1) | ((k.atan_deg >= 0 && k.atan_deg <= 4) ? 2 : 0);
+    switch (k.bp_kz) {
+        case 8: launch_bpT<8>(cls, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes); break;
+        case 32: launch_bpT<32>(cls, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes); break;
+        default: launch_bpT<16>(cls, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes); break;
     }
-    // plans with boxes beyond the LDS tile: per-tap global atomics
-    const int ns_eff = k.ns < k.nz ? k.ns : k.nz;
-    const int runs = (ns_eff + kKZ - 1) / kKZ;
-    dim3 grid((k.nx + kTile - 1) / kTile, (k.ny + kTile - 1) / kTile, (unsigned)(k.n_pitches * runs));
-    hipLaunchKernelGGL(k_backproject_T<kKZ>, grid, dim3(64), 0, s, k, gvol, gFbar, runs);
     return hipGetLastError();
 }
-
 
 }  // namespace kats

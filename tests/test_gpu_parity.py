@@ -325,6 +325,39 @@ def test_adjoint_matches_oracle_transpose(small_adj):
     assert rel <= REL_L2
 
 
+@pytest.mark.parametrize("case,bp_slices", [("fits", 8), ("fits", 32), ("hbm", 16), ("hbm", 8)])
+def test_adjoint_kernel_instances(case, bp_slices):
+    """The adjoint's kernel instances against the oracle's transpose: 8- and 32-slice runs,
+    and a 32-row detector whose footprint boxes (36 rows) exceed the LDS tile, so its views
+    scatter through the HBM path."""
+    dev = _dev()
+    if case == "fits":
+        wl = configs.tiny(nxy=12, nz=20, cols=40, rows=8, views_per_turn=60, turns=4, feed=24.0,
+                          dxy=2.5, slices_per_pitch=8)
+    else:
+        wl = configs.tiny(nxy=16, nz=16, cols=48, rows=32, views_per_turn=72, turns=4, feed=24.0,
+                          dxy=2.0, slices_per_pitch=12)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    plan = K.Plan(geom, gr, device=0, bp_slices=bp_slices)
+    lr = 64 if bp_slices >= 32 else 32
+    fits = plan.info["bp_box_rows"] <= lr and plan.info["bp_box_cols"] <= 64
+    assert fits == (case == "fits")
+    rng = np.random.default_rng(21)
+    fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
+    got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev)).cpu().numpy()
+    ref = O.recon_T(O.Scan(geom), gr, fbar.astype(np.float64))
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    x = torch.from_numpy(rng.normal(size=(geom["n_views"], geom["det_rows"], geom["det_cols"]))
+                         .astype(np.float32)).to(dev)
+    Ax = K.recon(plan, x).double()
+    lhs = float((Ax * torch.from_numpy(fbar).to(dev).double()).sum())
+    rhs = float((x.double() * torch.from_numpy(got).to(dev).double()).sum())
+    dot = abs(lhs - rhs) / (float(Ax.norm()) * float(np.linalg.norm(fbar)))
+    print(f"[parity] adjoint {case} bp_slices={bp_slices} (boxes {plan.info['bp_box_rows']}x"
+          f"{plan.info['bp_box_cols']}): vs oracle rel-L2 {rel:.3e}, dot product {dot:.3e}", flush=True)
+    assert rel <= REL_L2 and dot <= 1e-5
+
+
 def test_autograd_function_gradient(small_adj):
     dev = _dev()
     geom, gr = small_adj
