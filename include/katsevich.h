@@ -225,7 +225,7 @@ int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, flo
  * 4th), d_sparse float32 [n_lines][ns] with ns = ceil(cols / step), n_lines = n_views *
  * rows; d_full float32 [n_lines][cols] gets the linear interpolation in alpha between
  * neighbouring kept columns, and the last kept column's value beyond it (at most 2^34
- * output samples). */
+ * output samples).  n_lines = 0 does nothing (the pointers may then be null). */
 int katsevich_sparse_upsample(const float *d_sparse, float *d_full, int64_t n_lines, int32_t cols,
                               int32_t step, void *stream);
 
@@ -245,7 +245,7 @@ int katsevich_max(const float *d_x, uint64_t n, float *d_max, void *d_scratch,
  * u1 = ((a >> 40) + 1) 2^-24, u2 = (b >> 40) 2^-24, where elements 2k and 2k+1 take
  * (a, b) = (x0, x1) and (x2, x3) of the Philox4x64-10 block of counter (k, 0, 0, 0) and
  * key (seed, 0).  The transcendentals are the hardware's single-precision ones.  d_out
- * may equal d_in. */
+ * may equal d_in.  n = 0 does nothing (the pointers may then be null). */
 int katsevich_add_noise(const float *d_in, float *d_out, uint64_t n, const float *d_max, double I0,
                         double var, uint64_t seed, void *stream);
 

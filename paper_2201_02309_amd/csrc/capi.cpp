@@ -352,9 +352,10 @@ int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, flo
 int katsevich_sparse_upsample(const float *d_sparse, float *d_full, int64_t n_lines, int32_t cols,
                               int32_t step, void *stream) {
     g_err.clear();
-    if (!d_sparse || !d_full) return fail(KATS_EINVAL, "katsevich_sparse_upsample: null pointer");
     if (n_lines < 0 || cols < 1 || step < 1)
         return fail(KATS_EINVAL, "katsevich_sparse_upsample: need n_lines >= 0, cols >= 1, step >= 1");
+    if (n_lines == 0) return KATS_OK;                 // nothing to read or write
+    if (!d_sparse || !d_full) return fail(KATS_EINVAL, "katsevich_sparse_upsample: null pointer");
     if ((uint64_t)n_lines * (((uint64_t)cols + 3) / 4) >= (1ull << 32))
         return fail(KATS_EINVAL, "katsevich_sparse_upsample: more than 2^34 output samples");
     const int ns = (cols + step - 1) / step;
@@ -380,8 +381,9 @@ int katsevich_max(const float *d_x, uint64_t n, float *d_max, void *d_scratch, u
 int katsevich_add_noise(const float *d_in, float *d_out, uint64_t n, const float *d_max, double I0,
                         double var, uint64_t seed, void *stream) {
     g_err.clear();
-    if (!d_in || !d_out || !d_max) return fail(KATS_EINVAL, "katsevich_add_noise: null pointer");
     if (!(I0 > 1.0) || !(var >= 0.0)) return fail(KATS_EINVAL, "katsevich_add_noise: need I0 > 1 and var >= 0");
+    if (n == 0) return KATS_OK;                       // nothing to read or write
+    if (!d_in || !d_out || !d_max) return fail(KATS_EINVAL, "katsevich_add_noise: null pointer");
     hipError_t e = kats::launch_noise(d_in, d_out, n, d_max, (float)I0, (float)std::sqrt(var), seed,
                                       static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "katsevich_add_noise: launch");

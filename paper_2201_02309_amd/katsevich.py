@@ -369,6 +369,8 @@ def sparse_upsample(sparse, cols: int, step: int = 4, out=None):
     """katsevich_sparse_upsample: [..., ceil(cols/step)] sparse columns -> [..., cols]."""
     import torch
     _f32(sparse, "sparse")
+    if int(cols) < 1 or int(step) < 1:
+        raise KatsevichError(-1, f"need cols >= 1 and step >= 1 (got {cols}, {step})")
     ns = (int(cols) + int(step) - 1) // int(step)
     if sparse.shape[-1] != ns:
         raise KatsevichError(-3, f"sparse: last dimension {sparse.shape[-1]} != ceil(cols/step) = {ns}")

@@ -154,3 +154,19 @@ def test_data_path_full_size_sampled():
     print(f"[parity] full-volume metrics: rmse {r[0]:.12g} vs {e_rmse:.12g}, ssim {r[1]:.12g} vs "
           f"{e_ssim:.12g}", flush=True)
     assert abs(r[0] - e_rmse) <= 1e-9 * e_rmse and abs(r[1] - e_ssim) <= 1e-9
+
+
+def test_empty_inputs():
+    """Zero-length data: upsampling and noise do nothing (torch passes null pointers for
+    empty tensors), the maximum and the metrics of nothing are errors."""
+    dev = _dev()
+    up = K.sparse_upsample(torch.empty((0, 5, 32), device=dev), 128, 4)
+    assert tuple(up.shape) == (0, 5, 128)
+    e = torch.empty((0,), device=dev)
+    assert K.add_noise(e, d_max=torch.ones(1, device=dev)).numel() == 0
+    with pytest.raises(K.KatsevichError):
+        K.max_value(e)
+    with pytest.raises(K.KatsevichError):
+        K.rmse_ssim(e, e)
+    with pytest.raises(K.KatsevichError):
+        K.sparse_upsample(torch.empty((3, 1), device=dev), 0, 4)

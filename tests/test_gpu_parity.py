@@ -169,6 +169,29 @@ def test_recon_ragged_grids(shape):
         assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
 
 
+@pytest.mark.parametrize("dz_mm", [200.0, -200.0])
+def test_grid_beyond_the_scan_reconstructs_to_zero(dz_mm):
+    """Degenerate plan: the grid lies above (or below) every slice the helix covers, so no
+    voxel is valid and no view is filtered; recon writes zeros over a volume that held other
+    values, and the adjoint writes zeros over the whole sinogram."""
+    dev = _dev()
+    wl = configs.config1()
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    gr["z_first"] += dz_mm
+    print(f"[case] grid beyond the scan, z shifted {dz_mm} mm", flush=True)
+    plan = K.Plan(geom, gr, device=0)
+    assert plan.info["n_vv"] == 0 and plan.n_filtered == 0
+    assert not plan.export("valid").any()
+    g = torch.rand((geom["n_views"], geom["det_rows"], geom["det_cols"]), device=dev,
+                   generator=torch.Generator(dev).manual_seed(5))
+    vol = torch.full((gr["nz"], gr["ny"], gr["nx"]), 7.0, device=dev)
+    K.recon(plan, g, out=vol)
+    gs = torch.full_like(g, 7.0)
+    K.recon_backward(plan, torch.rand_like(vol), out=gs)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(vol)) == 0 and int(torch.count_nonzero(gs)) == 0
+
+
 def test_turn_shift_gives_pitch_shift_bit_exact():
     """Sinogram shifted by one turn (views_per_turn views) -> volume shifted by one pitch,
     bit for bit: every pitch uses identical pitch-relative geometry and no atomics."""

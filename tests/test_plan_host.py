@@ -93,6 +93,39 @@ def test_compute_on_unbound_plan_is_an_error():
     assert b"not bound" in p._lib.katsevich_last_error()
 
 
+def test_data_path_argument_checks():
+    """The plan-free data path rejects bad arguments before any launch (dummy addresses are
+    never dereferenced) and treats zero-length data as no work, with null pointers."""
+    import ctypes
+    lib = pk.load_library()
+    d = ctypes.c_void_p(256)
+    misaligned = ctypes.c_void_p(256 + 4)
+    null = ctypes.c_void_p(0)
+    up = lib.katsevich_sparse_upsample
+    assert up(null, null, 0, 736, 4, None) == 0
+    assert up(d, d, -1, 736, 4, None) == -1
+    assert up(d, d, 10, 0, 4, None) == -1
+    assert up(d, d, 10, 736, 0, None) == -1
+    assert up(null, d, 10, 736, 4, None) == -1
+    assert up(d, d, 1 << 32, 8, 4, None) == -1                  # 2^34 output samples
+    assert b"2^34" in lib.katsevich_last_error()
+    sb = int(lib.katsevich_data_scratch_bytes())
+    assert sb > 0
+    mx = lib.katsevich_max
+    assert mx(d, 0, d, d, sb, None) == -1                        # max of nothing
+    assert mx(d, 10, d, d, sb - 1, None) == -4
+    assert mx(d, 10, d, misaligned, sb, None) == -1
+    nz = lib.katsevich_add_noise
+    assert nz(null, null, 0, null, 1e5, 0.5, 1, None) == 0
+    assert nz(d, d, 10, d, 1.0, 0.5, 1, None) == -1               # I0 must exceed 1
+    assert nz(d, d, 10, d, 1e5, -0.5, 1, None) == -1
+    assert nz(d, d, 10, null, 1e5, 0.5, 1, None) == -1
+    ms = lib.katsevich_rmse_ssim
+    assert ms(d, d, 0, d, d, sb, None) == -1
+    assert ms(d, d, 10, d, d, sb - 1, None) == -4
+    assert ms(d, d, 10, d, misaligned, sb, None) == -1
+
+
 def _compare_tables(wl, n_sample=None, seed=0, half=False):
     g = wl.geom.as_dict()
     scan = O.Scan(O.half_sample_geometry(g) if half else g, wl.n_psi)
