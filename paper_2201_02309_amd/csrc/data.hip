@@ -28,7 +28,9 @@ constexpr int kThreads = 256;
 // ---------------------------------------------------------------- upsampling
 // Thread q takes output columns 4p .. 4p+3 (p = q mod slots) of line q / slots: one 32-bit
 // division per thread, the kept-column index advanced incrementally, one 16-byte store
-// when rows of the output are 16-byte aligned (cols a multiple of 4).
+// when rows of the output are 16-byte aligned (cols a multiple of 4).  With step 4 (the
+// paper's decimation) the four columns lie between kept columns p and p + 1, so two loads
+// serve them; the arithmetic is the general path's.
 __global__ __launch_bounds__(kThreads) void k_upsample(const float *__restrict__ sp, float *__restrict__ full,
                                                        unsigned lines, int cols, int ns, int step) {
     const unsigned slots = ((unsigned)cols + 3u) / 4u;
@@ -39,19 +41,32 @@ __global__ __launch_bounds__(kThreads) void k_upsample(const float *__restrict__
         const unsigned line = q / slots;
         const int c0 = (int)(q - line * slots) * 4;
         const float *s = sp + (size_t)line * ns;
-        int j = c0 / step, k = c0 - j * step;
         float v[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        if (step == 4) {
+            const int j = c0 >> 2;
             if (j + 1 < ns) {
-                const float a = s[j], b = s[j + 1];
-                v[t] = fmaf((float)k * inv_step, b - a, a);
+                const float a = s[j], d = s[j + 1] - a;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v[t] = fmaf((float)t * inv_step, d, a);
             } else {
-                v[t] = s[ns - 1];
+                const float h = s[ns - 1];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v[t] = h;
             }
-            if (++k == step) {
-                k = 0;
-                ++j;
+        } else {
+            int j = c0 / step, k = c0 - j * step;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (j + 1 < ns) {
+                    const float a = s[j], b = s[j + 1];
+                    v[t] = fmaf((float)k * inv_step, b - a, a);
+                } else {
+                    v[t] = s[ns - 1];
+                }
+                if (++k == step) {
+                    k = 0;
+                    ++j;
+                }
             }
         }
         float *o = full + (size_t)line * cols + c0;
@@ -70,9 +85,17 @@ struct U64x4 {
     uint64_t v[4];
 };
 
+// Full 128-bit product hi:lo of two 64-bit words from four 32 x 32 -> 64 products, each
+// carry folded into the next product's addend (one v_mad_u64_u32 apiece): with t = a0 b1 +
+// hi(a0 b0) and u = a1 b0 + lo(t), a b = lo(a0 b0) + 2^32 u + 2^64 (a1 b1 + hi(t)).
 __device__ inline void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
-    lo = a * b;
-    hi = __umul64hi(a, b);
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t p00 = (uint64_t)a0 * b0;
+    const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);
+    const uint64_t u = (uint64_t)a1 * b0 + (uint32_t)t;
+    lo = (u << 32) | (uint32_t)p00;
+    hi = (uint64_t)a1 * b1 + ((t >> 32) + (u >> 32));
 }
 
 // Philox4x64 with 10 rounds (Salmon et al., SC'11): round multipliers 0xD2E7470EE14C6C93 and
@@ -96,15 +119,16 @@ __device__ inline U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
 }
 
 // One pair of elements per thread.  Transcendentals are the hardware's: v_log_f32 (log2),
-// v_exp_f32 (2^x), v_sin_f32 / v_cos_f32 (argument in turns), v_rcp_f32.
+// v_exp_f32 (2^x), v_sin_f32 / v_cos_f32 (argument in turns), v_rcp_f32, v_sqrt_f32 (its
+// arguments here are 0 or normal: -2 ln u1 in [0, 33.3], lambda >= I0 / e).
 __device__ inline float noisy_value(float g, uint64_t w0, uint64_t w1, float M, float inv_M_log2e, float I0,
                                     float sd_e) {
     const float u1 = (float)((w0 >> 40) + 1) * 5.9604644775390625e-8f;     // (0, 1]
     const float u2 = (float)(w1 >> 40) * 5.9604644775390625e-8f;           // [0, 1)
-    const float rho = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));   // sqrt(-2 ln u1)
+    const float rho = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));   // sqrt(-2 ln u1)
     const float z1 = rho * __builtin_amdgcn_cosf(u2), z2 = rho * __builtin_amdgcn_sinf(u2);
     const float lam = I0 * __builtin_amdgcn_exp2f(-g * inv_M_log2e);
-    float counts = fmaf(sqrtf(lam), z1, lam) + sd_e * z2;
+    float counts = fmaf(__builtin_amdgcn_sqrtf(lam), z1, lam) + sd_e * z2;
     counts = fmaxf(counts, 1.0f);
     return M * 0.69314718055994531f * __builtin_amdgcn_logf(I0 * __builtin_amdgcn_rcpf(counts));
 }
