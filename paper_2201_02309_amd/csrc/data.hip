@@ -24,13 +24,14 @@ namespace kats {
 namespace {
 
 constexpr int kThreads = 256;
+typedef float F4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- upsampling
 // Thread q takes output columns 4p .. 4p+3 (p = q mod slots) of line q / slots: one 32-bit
 // division per thread, the kept-column index advanced incrementally, one 16-byte store
-// when rows of the output are 16-byte aligned (cols a multiple of 4).  With step 4 (the
-// paper's decimation) the four columns lie between kept columns p and p + 1, so two loads
-// serve them; the arithmetic is the general path's.
+// (non-temporal) when rows of the output are 16-byte aligned (cols a multiple of 4).  With
+// step 4 (the paper's decimation) the four columns lie between kept columns p and p + 1, so
+// two loads serve them; the arithmetic is the general path's.
 __global__ __launch_bounds__(kThreads) void k_upsample(const float *__restrict__ sp, float *__restrict__ full,
                                                        unsigned lines, int cols, int ns, int step) {
     const unsigned slots = ((unsigned)cols + 3u) / 4u;
@@ -70,8 +71,9 @@ __global__ __launch_bounds__(kThreads) void k_upsample(const float *__restrict__
             }
         }
         float *o = full + (size_t)line * cols + c0;
-        if (vec) {
-            *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
+        if (vec) {      // streaming store: the output is not read again here
+            const F4 w = {v[0], v[1], v[2], v[3]};
+            __builtin_nontemporal_store(w, reinterpret_cast<F4 *>(o));
         } else {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
