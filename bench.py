@@ -302,9 +302,8 @@ def main():
                     help="slices per backprojection register run (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding by pitch ranges is described in the "
-                                   "design notes, not built)"}))
+        print(json.dumps({"error": "the reconstructor runs on one GPU; --gpus must be 1 "
+                                   "(sharding by pitch ranges across GPUs is not implemented)"}))
         sys.exit(2)
 
     import numpy as np

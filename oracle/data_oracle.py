@@ -6,7 +6,7 @@ with the HIP library.
 * Sec. III-C data preparation: keep every 4th detector column (alpha_sp = alpha[0:4:end]),
   interpolate back to the full column grid, add 'Gaussian+Poisson' noise:
   counts from lambda = I0 exp(-g / M) (M the maximum of the upsampled sinogram), then
-  g_in = M log(I0 / counts).  Readings (one each, listed in the design notes):
+  g_in = M log(I0 / counts).  Readings where the paper leaves a choice:
   - interpolation: linear in alpha between neighbouring kept columns, the last kept
     column's value held beyond it (numpy.interp's end rule);
   - the printed 'g = g + poisson(g) + Gaussian' is taken as counts = Poisson(lambda) +

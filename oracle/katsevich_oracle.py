@@ -8,7 +8,7 @@ Sec. II of the paper (derivative at constant direction, length-correction weight
 forward height rebinning onto kappa-lines, 1-D Hilbert transform in alpha, backward
 height rebinning, post-cosine weighting, PI-window backprojection), in the paper's
 order and notation.  Points the paper leaves open are fixed as follows (one reading
-each, listed with reasons in the design notes):
+each):
 
 * derivative: central differences in lambda and alpha on the native grid, detector
   data taken as 0 outside the columns; the first and last acquired views get no
