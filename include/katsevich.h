@@ -189,13 +189,15 @@ int katsevich_recon(katsevich_plan_t plan, const float *d_sino, float *d_vol,
  * first_view..last_view with a zero border: gf_rows = rows + 2*KATS_GF_PAD, gf_cols =
  * cols + 2*KATS_GF_PAD rounded up to a multiple of 4, element [v][r+KATS_GF_PAD][c+KATS_GF_PAD]
  * is detector cell (r, c) and every other element is 0.
- * d_ws: at least workspace_bytes_filter.  Asynchronous on stream. */
+ * d_ws: at least workspace_bytes_filter.  Asynchronous on stream.  Errors: KATS_EINVAL,
+ * KATS_ENOTBOUND, KATS_EWORKSPACE, KATS_EHIP. */
 #define KATS_GF_PAD 2
 int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF,
                      void *d_ws, uint64_t ws_bytes, void *stream);
 
 /* Backprojection stage alone (backprojection step of Sec. II, every pitch reusing the
- * first pitch's tables): d_gF as written by katsevich_filter -> d_vol.  Asynchronous. */
+ * first pitch's tables): d_gF as written by katsevich_filter -> d_vol.  Asynchronous.
+ * Errors: KATS_EINVAL, KATS_ENOTBOUND, KATS_EHIP. */
 int katsevich_backproject(katsevich_plan_t plan, const float *d_gF, float *d_vol, void *stream);
 
 /* Grouped backprojection of n reconstructions (serving): item i backprojects d_gF[i]
@@ -212,7 +214,8 @@ int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *cons
 
 /* Exact adjoint of katsevich_recon (transpose of the discrete operator): d_grad_vol
  * float32 [nz][ny][nx] -> d_grad_sino float32 [n_views][rows][cols] (overwritten).
- * d_ws: at least workspace_bytes.  Asynchronous on stream. */
+ * d_ws: at least workspace_bytes.  Asynchronous on stream.  Errors: KATS_EINVAL,
+ * KATS_ENOTBOUND, KATS_EWORKSPACE, KATS_EHIP. */
 int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, float *d_grad_sino,
                              void *d_ws, uint64_t ws_bytes, void *stream);
 
