@@ -423,12 +423,13 @@ def main():
                    "bp_slices": args.bp_slices or 16},
         "volumes_per_s": round(1e3 / ms_step, 3),
         "stage_ms": {"filter": round(float(np.mean(filt_ms)), 4), "backproject": round(bp_avg, 4)},
+        "backproject_gvoxel_view_per_s": round(n_vv / (bp_avg * 1e-3) / 1e9, 3),
         "recon_call_ms": round(recon_ms, 4),
         "adjoint_call_ms": round(adjoint_ms, 3),
         "half_sample_recon_call_ms": round(half_ms, 4),
         "plan_build_s": round(t_plan, 3),
         "plan_build_gpu_pi_s": round(t_plan_gpu, 3),
-        "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": round(achieved, 3),
+        "roofline": {"kernel": "k_bp_lds", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
                      "flop_per_update": BP_FLOP_PER_UPDATE},
