@@ -37,6 +37,11 @@ using namespace bpdev;
 // the fallback reads those views' taps from the zero-padded g^F in HBM instead.
 // ---------------------------------------------------------------------------------
 constexpr int kHull = 2048;       // max views of a workgroup hull with per-view group words
+// LDS row pitch of the box tile (floats): 72 instead of the 64 box columns moves each row
+// by eight banks, so lanes reading one column at different rows meet fewer conflicts
+// (9.11 ms against 9.15 ms on the clinical workload; the adjoint gains far more from the
+// same padding)
+constexpr int kRowF = 72;
 
 template <class P>
 __device__ inline float lerp_bilinear(P t, int pitch_f, float tc, float tr) {
@@ -49,7 +54,7 @@ __device__ inline float lerp_bilinear(P t, int pitch_f, float tc, float tr) {
 // Shared memory of one backprojection workgroup.
 template <int KZ>
 struct BpShared {
-    __attribute__((aligned(16))) float tile[2][kLP * lds_rows<KZ>()];   // double-buffered box
+    __attribute__((aligned(16))) float tile[2][kRowF * lds_rows<KZ>()];   // double-buffered box
     unsigned short words[4][kHull];  // per wave and view: active groups | full groups << 8
     int red[8];
 };
@@ -170,7 +175,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
 #pragma unroll
             for (int k = 0; k < NP; ++k)
                 if (srow + 16 * k < b.nr && scol < b.nc)
-                    *reinterpret_cast<float4 *>(&lds[0][(srow + 16 * k) * kLP + scol]) =
+                    *reinterpret_cast<float4 *>(&lds[0][(srow + 16 * k) * kRowF + scol]) =
                         ldg(reinterpret_cast<const float4 *>(src + (srow + 16 * k) * cpitch + scol));
         }
     }
@@ -254,7 +259,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
             const float *T = &lds[buf][c0];
 #pragma unroll
             for (int g = 0; g < NG; ++g)
-                if (word & (1u << g)) group(T, kLP, g);
+                if (word & (1u << g)) group(T, kRowF, g);
         } else {
             const auto T = glb(gF0 + (size_t)m * vstride + (b.r0 + kPad) * cpitch + (b.c0 + kPad) + c0);
 #pragma unroll
@@ -265,7 +270,7 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
             float *Dst = lds[buf ^ 1];
 #pragma unroll
             for (int k = 0; k < NP; ++k)
-                if (stg[k]) *reinterpret_cast<float4 *>(&Dst[(srow + 16 * k) * kLP + scol]) = pf[k];
+                if (stg[k]) *reinterpret_cast<float4 *>(&Dst[(srow + 16 * k) * kRowF + scol]) = pf[k];
         }
         b = bn;
         bw_next = bw_after;

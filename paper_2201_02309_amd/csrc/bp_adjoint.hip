@@ -21,7 +21,14 @@ using namespace bpdev;
 // several times faster here than its float32 one, and exact enough that the flushed float32
 // sums round once.  Group words are bytes while the groups fit in 4 bits, so that the
 // double-buffered boxes still leave room for four workgroups per CU.
-constexpr int kLPT = kLP;
+constexpr int kLPT = kLP;         // box columns
+// LDS row pitch of the boxes (doubles): 64 would put a column's cells of every row in one
+// bank pair, so lanes scattering to one column at different rows would conflict; 66 moves
+// each row by four banks.  Measured on the whole adjoint: clinical 512^2 x 128 workload
+// 47.0 ms against 56.8 ms (65, 68, 70, 72 and 80 were slower than 66); the 16-row network
+// window 3.76 ms against 3.30 ms and the 184-column sparse detector 53.7 ms against 51.7 ms,
+// where lanes at other column and row offsets meet in the shifted banks instead.
+constexpr int kRowT = 66;
 constexpr int kHullT = 2000;
 
 template <int KZ>
@@ -29,7 +36,7 @@ struct BpTShared {
     static constexpr int NG = KZ / kKG;
     using Word = typename std::conditional<(NG <= 4), unsigned char, unsigned short>::type;
     static constexpr int kFull = NG <= 4 ? 4 : 8;
-    __attribute__((aligned(16))) double box[2][kLPT * lds_rows<KZ>()];
+    __attribute__((aligned(16))) double box[2][kRowT * lds_rows<KZ>()];
     Word words[4][kHullT];
     int red[8];
 };
@@ -104,7 +111,7 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         red[4 + wave] = whi;
     }
     // both box buffers start zeroed (every flush leaves its cells zero again)
-    for (int i = tid; i < 2 * kLPT * kLR; i += kNT) (&box[0][0])[i] = 0.0;
+    for (int i = tid; i < 2 * kRowT * kLR; i += kNT) (&box[0][0])[i] = 0.0;
     __syncthreads();
     const int mlo = __builtin_amdgcn_readfirstlane(min(min(red[0], red[1]), min(red[2], red[3])));
     const int mhi = __builtin_amdgcn_readfirstlane(max(max(red[4], red[5]), max(red[6], red[7])));
@@ -138,7 +145,7 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         float *img = gFbar + (size_t)(base + m - first_view) * vstride;
         const int cc = tid & 63;
         for (int rr = tid >> 6; rr < b.nr; rr += 4) {
-            double *cell = bx + rr * kLPT + cc;
+            double *cell = bx + rr * kRowT + cc;
             const double v = *cell;
             if (v != 0.0) {
                 *cell = 0.0;
@@ -217,7 +224,7 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
             walk([&](int row, float v) {
                 if (v != 0.0f) {
                     const float v1 = v * tc;
-                    double *cell = bx + row * kLPT;
+                    double *cell = bx + row * kRowT;
                     atomicAdd(cell, (double)(v - v1));
                     atomicAdd(cell + 1, (double)v1);
                 }
