@@ -24,12 +24,14 @@ using namespace bpdev;
 constexpr int kLPT = kLP;         // box columns
 // LDS row pitch of the boxes (doubles): 64 would put a column's cells of every row in one
 // bank pair, so lanes scattering to one column at different rows would conflict; 66 moves
-// each row by four banks.  Measured on the whole adjoint: clinical 512^2 x 128 workload
-// 47.0 ms against 56.8 ms (65, 68, 70, 72 and 80 were slower than 66); the 16-row network
-// window 3.76 ms against 3.30 ms and the 184-column sparse detector 53.7 ms against 51.7 ms,
-// where lanes at other column and row offsets meet in the shifted banks instead.
+// each row by four banks (65, 68, 70, 72 and 80 were slower).  The hull's word table is
+// sized so that a 16-slice workgroup still takes exactly 40960 bytes, four per CU: views
+// of hulls up to 1784 long (the largest hull of the 512^3 / 55296-view workload is 1649).
+// Whole adjoint against 64-double rows: clinical 512^2 x 128 workload 44.3 ms against
+// 56.8 ms, 16-row network window 2.82 against 3.30 ms, 184-column sparse detector 51.1
+// against 51.7 ms.
 constexpr int kRowT = 66;
-constexpr int kHullT = 2000;
+constexpr int kHullT = 1784;
 
 template <int KZ>
 struct BpTShared {
