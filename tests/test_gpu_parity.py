@@ -169,6 +169,44 @@ def test_recon_ragged_grids(shape):
         assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
 
 
+def test_long_hulls_take_the_exact_fallback():
+    """3000 views per turn: a workgroup's hull (the union of its voxels' PI windows over a
+    pitch) spans ~4200 views, beyond the per-view group-word tables of both backprojectors,
+    which then evaluate every slice group's coverage at every view.  Forward against the
+    oracle, adjoint against the oracle transpose and by the dot product."""
+    dev = _dev()
+    wl = configs.tiny(nxy=16, nz=8, cols=48, rows=8, views_per_turn=3000, turns=3, feed=24.0,
+                      dxy=2.0, slices_per_pitch=8)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    print("[case] long hulls, 3000 views per turn", flush=True)
+    plan = K.Plan(geom, gr, device=0)
+    nf, nl = plan.export("pi_nfirst").astype(np.int64), plan.export("pi_nlast").astype(np.int64)
+    ok = nf <= nl
+    assert ok.any() and int(nl[ok].max() - nf[ok].min() + 1) > 2048
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    sino = phantom.project(ph, geom).astype(np.float32)
+    scan = O.Scan(geom)
+    ref, valid = O.recon(scan, gr, sino)
+    vol = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
+    peak = max(float(phantom.density(ph, _grid_points(gr)).max()), 0.1)
+    rel, mx = _report("long hulls", vol, ref, valid, peak)
+    assert valid.any() and np.all(vol[~valid] == 0)
+    assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
+    rng = np.random.default_rng(8)
+    fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
+    got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev))
+    ref_T = O.recon_T(scan, gr, fbar.astype(np.float64))
+    rel_T = np.linalg.norm(got.cpu().numpy() - ref_T) / np.linalg.norm(ref_T)
+    x = torch.from_numpy(sino).to(dev)
+    Ax = K.recon(plan, x).double()
+    y = torch.from_numpy(fbar).to(dev).double()
+    dot = abs(float((Ax * y).sum()) - float((x.double() * got.double()).sum()))
+    dot /= float(Ax.norm()) * float(y.norm())
+    print(f"[parity] long hulls adjoint: vs oracle rel-L2 {rel_T:.3e}, dot product {dot:.3e}",
+          flush=True)
+    assert rel_T <= REL_L2 and dot <= 1e-5
+
+
 @pytest.mark.parametrize("dz_mm", [200.0, -200.0])
 def test_grid_beyond_the_scan_reconstructs_to_zero(dz_mm):
     """Degenerate plan: the grid lies above (or below) every slice the helix covers, so no
