@@ -137,7 +137,8 @@ __device__ void bp_tile(const BpArgs p, const float *__restrict__ gF, float *__r
     const int mhi = __builtin_amdgcn_readfirstlane(max(max(red[4], red[5]), max(red[6], red[7])));
     // Per-view group classification of this wave.  A hull longer than kHull views
     // takes the coverage path for every group at every view, which is exact.
-    const bool use_words = mhi - mlo + 1 <= kHull;
+    // (an empty hull, mlo = INT_MAX > mhi = INT_MIN, takes no words: mhi - mlo would overflow)
+    const bool use_words = mlo <= mhi && mhi - mlo < kHull;
     if (use_words) {
         for (int w = lane; w <= mhi - mlo; w += 64) {
             const int m = mlo + w;

@@ -119,7 +119,8 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     const int mhi = __builtin_amdgcn_readfirstlane(max(max(red[4], red[5]), max(red[6], red[7])));
     using Word = typename BpTShared<KZ>::Word;
     constexpr int kFull = BpTShared<KZ>::kFull;
-    const bool use_words = mhi - mlo + 1 <= kHullT;
+    // (an empty hull, mlo = INT_MAX > mhi = INT_MIN, takes no words: mhi - mlo would overflow)
+    const bool use_words = mlo <= mhi && mhi - mlo < kHullT;
     if (use_words) {
         for (int w = lane; w <= mhi - mlo; w += 64) {
             const int m = mlo + w;

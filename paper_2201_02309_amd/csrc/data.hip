@@ -35,10 +35,16 @@ typedef float F4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(kThreads) void k_upsample(const float *__restrict__ sp, float *__restrict__ full,
                                                        unsigned lines, int cols, int ns, int step) {
     const unsigned slots = ((unsigned)cols + 3u) / 4u;
-    const unsigned total = lines * slots;                      // < 2^32 (host check)
+    const unsigned long long total = (unsigned long long)lines * slots;   // < 2^32 (host check)
     const bool vec = (cols & 3) == 0 && ((uintptr_t)full & 15) == 0;
     const float inv_step = 1.0f / (float)step;
-    for (unsigned q = blockIdx.x * kThreads + threadIdx.x; q < total; q += gridDim.x * kThreads) {
+    // the loop index is 64-bit: with a total just below 2^32 a 32-bit index would wrap on
+    // its last stride and never reach the bound; inside the loop it is below 2^32, so the
+    // line / slot split stays a 32-bit division
+    const unsigned long long stride = (unsigned long long)gridDim.x * kThreads;
+    for (unsigned long long qq = (unsigned long long)blockIdx.x * kThreads + threadIdx.x; qq < total;
+         qq += stride) {
+        const unsigned q = (unsigned)qq;
         const unsigned line = q / slots;
         const int c0 = (int)(q - line * slots) * 4;
         const float *s = sp + (size_t)line * ns;

@@ -47,6 +47,9 @@ class Request:
     geom: dict
     grid: dict
     sino: object                 # device tensor [n_views, rows, cols] (read only)
+    # event recorded on the stream that wrote sino (None: sino was complete before run());
+    # the serving stream waits for it before reading the sinogram
+    ready: object = None
     # filled by the server
     t_plan_ready: float = float("nan")
     t_admit: float = float("nan")
@@ -56,10 +59,15 @@ class Request:
     footprint: int = 0
     offset: int = 0              # arena byte offset while in flight
     volume: object = None
+    error: str = ""              # non-empty: rejected (plan failed or footprint too large)
 
     @property
     def latency(self):
         return self.t_done - self.arrival
+
+
+class PlanFailed(RuntimeError):
+    """The plan of a request's geometry could not be built."""
 
 
 class PlanCache:
@@ -72,6 +80,7 @@ class PlanCache:
         self.gpu_plan = gpu_plan                   # PI lines on the GPU (katsevich_plan_device)
         self.plans = {}
         self.pending = {}
+        self.failed = {}
         self.build_seconds = {}
         self.hits = self.misses = 0
         self.table_bytes = 0
@@ -107,14 +116,23 @@ class PlanCache:
             return key, False
 
     def poll(self, key):
-        """Plan of key if built (moving it into the cache), else None."""
+        """Plan of key if built (moving it into the cache), else None; raises
+        PlanFailed if its build failed (every later poll of that key raises too)."""
         with self._lock:
             if key in self.plans:
                 return self.plans[key]
+            if key in self.failed:
+                raise PlanFailed(self.failed[key])
             fut = self.pending.get(key)
         if fut is None or not fut.done():
             return None
-        plan, secs = fut.result()
+        try:
+            plan, secs = fut.result()
+        except Exception as exc:                      # a geometry the library rejects
+            with self._lock:
+                self.failed[key] = f"plan build failed: {exc}"
+                self.pending.pop(key, None)
+            raise PlanFailed(self.failed[key]) from exc
         with self._lock:
             if key not in self.plans:
                 self.plans[key] = plan
@@ -124,6 +142,7 @@ class PlanCache:
             return self.plans[key]
 
     def get_blocking(self, geom, grid):
+        """Plan of (geom, grid), waiting for its build (raises PlanFailed)."""
         key, _ = self.request(geom, grid)
         while True:
             p = self.poll(key)
@@ -252,6 +271,9 @@ class Server:
         with torch.cuda.stream(s):
             for r, plan in batch:
                 sino, ws, gF, vol = self._views(r, plan)
+                if r.ready is not None:                    # the producer's writes first
+                    s.wait_event(r.ready)
+                r.sino.record_stream(s)                    # read here: keep it alive for s
                 sino.copy_(r.sino)                         # D2D copy into the request's slot
                 K.filter_views(plan, sino, out=gF, ws=ws)
                 plans.append(plan)
@@ -261,6 +283,13 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(s)
         return ev, vols
+
+    @staticmethod
+    def _reject(r, why, t0, done):
+        """Complete request r with an error; the loop goes on with the others."""
+        r.error = why
+        r.t_done = time.perf_counter() - t0
+        done.append(r)
 
     def run(self, requests, clock_start=None):
         """Serve requests (sorted by arrival); returns them with timings filled in."""
@@ -301,7 +330,11 @@ class Server:
                 blocked = False
                 work = 0.0
                 for r, key in waiting:
-                    plan = self.cache.poll(key)
+                    try:
+                        plan = self.cache.poll(key)
+                    except PlanFailed as exc:
+                        self._reject(r, str(exc), t0, done)
+                        continue
                     if plan is None:
                         rest.append((r, key))
                         continue
@@ -309,6 +342,10 @@ class Server:
                         r.t_plan_ready = time.perf_counter() - t0
                         r.plan_seconds = self.cache.build_seconds.get(key, 0.0)
                         r.footprint = footprint(plan)
+                        if r.footprint > self.arena.size:
+                            self._reject(r, f"footprint {r.footprint} B exceeds the budget "
+                                            f"{self.arena.size} B", t0, done)
+                            continue
                     off = None
                     if not blocked and len(batch) < self.max_batch and \
                             (not batch or work < self.group_work):
@@ -343,9 +380,16 @@ def serve_sequential(plan_cache: PlanCache, requests, keep_volumes=False):
             time.sleep(0.0002)
         key, hit = plan_cache.request(r.geom, r.grid)
         r.cache_hit = hit
-        plan = plan_cache.get_blocking(r.geom, r.grid)
+        try:
+            plan = plan_cache.get_blocking(r.geom, r.grid)
+        except PlanFailed as exc:
+            r.error = str(exc)
+            r.t_done = time.perf_counter() - t0
+            continue
         r.t_plan_ready = r.t_admit = time.perf_counter() - t0
         r.plan_seconds = plan_cache.build_seconds.get(key, 0.0)
+        if r.ready is not None:
+            torch.cuda.current_stream(r.sino.device).wait_event(r.ready)
         sino = r.sino.clone()
         vol = K.recon(plan, sino)
         torch.cuda.current_stream(sino.device).synchronize()
@@ -357,6 +401,8 @@ def serve_sequential(plan_cache: PlanCache, requests, keep_volumes=False):
 
 
 def summarize(reqs):
+    rejected = [r for r in reqs if r.error]
+    reqs = [r for r in reqs if not r.error]
     lat = np.array([r.latency for r in reqs])
     first = min(r.arrival for r in reqs)
     last = max(r.t_done for r in reqs)
@@ -364,4 +410,4 @@ def summarize(reqs):
             "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_latency_ms": float(lat.mean() * 1e3), "makespan_s": float(last - first),
             "volumes_per_s": float(len(reqs) / max(last - first, 1e-9)),
-            "cache_hits": int(sum(r.cache_hit for r in reqs))}
+            "cache_hits": int(sum(r.cache_hit for r in reqs)), "rejected": len(rejected)}

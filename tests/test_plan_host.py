@@ -109,6 +109,11 @@ def test_data_path_argument_checks():
     assert up(null, d, 10, 736, 4, None) == -1
     assert up(d, d, 1 << 32, 8, 4, None) == -1                  # 2^34 output samples
     assert b"2^34" in lib.katsevich_last_error()
+    # the smallest rejected size: 512 columns are 128 four-column slots per line, and 2^25
+    # lines make exactly 2^32 slots, the kernel's 64-bit loop bound (2^25 - 1 lines pass
+    # the check; not launched here, the addresses are dummies)
+    assert up(d, d, 1 << 25, 512, 4, None) == -1
+    assert b"2^34" in lib.katsevich_last_error()
     sb = int(lib.katsevich_data_scratch_bytes())
     assert sb > 0
     mx = lib.katsevich_max

@@ -43,3 +43,32 @@ def test_plan_key_distinguishes_geometries():
     assert plan_key(g, gr) != plan_key(dict(g, feed_per_turn=50.0000001), gr)
     assert plan_key(g, gr) != plan_key(g, dict(gr, nx=9))
     assert plan_key(g, gr, bp_slices=8) != plan_key(g, gr)
+
+
+def test_failed_plan_build_is_reported_per_request():
+    """A geometry whose plan cannot be built fails that key only: poll raises PlanFailed on
+    every later call, and other keys keep working (the server rejects the request with an
+    error instead of stopping its loop)."""
+    import time
+
+    from paper_2201_02309_amd.serve import PlanCache, PlanFailed
+
+    cache = PlanCache(device=None, workers=1)
+
+    def build(geom, grid):
+        if geom["feed_per_turn"] < 0:
+            raise ValueError("feed must be positive")
+        return type("P", (), {"info": {"table_bytes": 256}})(), 0.0
+    cache._build = build
+    g = {"R": 570.0, "D": 1040.0, "feed_per_turn": 50.0, "n_views": 100}
+    gr = {"nx": 8, "dx": 1.0}
+    bad, _ = cache.request(dict(g, feed_per_turn=-1.0), gr)
+    good, _ = cache.request(g, gr)
+    deadline = time.time() + 10
+    while cache.poll(good) is None and time.time() < deadline:
+        time.sleep(0.01)
+    assert cache.poll(good) is not None
+    for _ in range(2):
+        with pytest.raises(PlanFailed, match="feed must be positive"):
+            cache.poll(bad)
+    cache.close()
