@@ -220,6 +220,18 @@ def network_pitch(nxy=512, dxy=1.0, cols=627, rows=16, views_per_turn=360, turns
                     seed=seed)
 
 
+def with_helix_offsets(wl: Workload, lambda0=0.7, z0=-13.2, lambda_first=0.31) -> Workload:
+    """The same workload on a helix with the source at angle lambda0 and height z0 at
+    lambda = 0 and the first view at lambda_first (not on the view grid), the grid moved
+    with the helix (centred on its new mid-height)."""
+    geom = Geometry(**dict(wl.geom.as_dict(), lambda0=lambda0, z0=z0, lambda_first=lambda_first))
+    g = wl.grid
+    grid = centred_grid(geom, g.nx, g.ny, g.nz, g.dx, g.dz)
+    grid.x_first, grid.y_first = g.x_first, g.y_first
+    return Workload(name=wl.name + "-offsets", geom=geom, grid=grid, phantom=dict(wl.phantom),
+                    seed=wl.seed, n_psi=wl.n_psi, batch=wl.batch)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
 
 

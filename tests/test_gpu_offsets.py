@@ -1,0 +1,129 @@
+"""GPU parity on helices with offsets (Sec. II helix: source angle lambda0 and height z0 at
+lambda = 0, first view off the view grid) and on grids whose slice spacing does not divide
+the feed (no per-pitch reuse: the whole grid is one table pitch).  Same bars as the other
+parity tests: relative L2 <= 1e-5 and max |error| <= 1e-4 of the phantom peak over valid
+voxels, invalid voxels exactly 0; the adjoint against the oracle's transpose and by the dot
+product."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs, phantom
+
+torch = pytest.importorskip("torch")
+K = pytest.importorskip("paper_2201_02309_amd")
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+MAX_ABS_OF_PEAK = 1e-4
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _points(gr):
+    x = gr["x_first"] + np.arange(gr["nx"]) * gr["dx"]
+    y = gr["y_first"] + np.arange(gr["ny"]) * gr["dy"]
+    z = gr["z_first"] + np.arange(gr["nz"]) * gr["dz"]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return np.stack([X, Y, Z], -1)
+
+
+def _recon_parity(name, geom, gr, ph_recipe, seed):
+    dev = _dev()
+    print(f"[case] {name}: lambda0 {geom['lambda0']} z0 {geom['z0']} "
+          f"lambda_first {geom['lambda_first']} dz {gr['dz']}", flush=True)
+    ph = phantom.make_phantom(ph_recipe, gr, seed)
+    sino = phantom.project(ph, geom).astype(np.float32)
+    ref, valid = O.recon(O.Scan(geom), gr, sino)
+    plan = K.Plan(geom, gr, device=0)
+    assert np.array_equal(valid, plan.export("valid").astype(bool))
+    vol = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
+    peak = float(phantom.density(ph, _points(gr)).max())
+    d = (vol - ref)[valid]
+    rel = float(np.linalg.norm(d) / np.linalg.norm(ref[valid]))
+    mx = float(np.abs(d).max())
+    print(f"[parity] {name}: rel-L2 {rel:.3e} max-abs {mx:.3e} peak {peak:.3f} "
+          f"valid {int(valid.sum())}", flush=True)
+    assert valid.sum() > 1000
+    assert np.all(vol[~valid] == 0)
+    assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
+    return plan
+
+
+def _adjoint_parity(name, geom, gr, seed):
+    dev = _dev()
+    print(f"[case] {name} adjoint", flush=True)
+    plan = K.Plan(geom, gr, device=0)
+    rng = np.random.default_rng(seed)
+    fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
+    got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev)).cpu().numpy()
+    ref = O.recon_T(O.Scan(geom), gr, fbar.astype(np.float64))
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    x = torch.from_numpy(rng.normal(size=(geom["n_views"], geom["det_rows"], geom["det_cols"]))
+                         .astype(np.float32)).to(dev)
+    Ax = K.recon(plan, x).double()
+    lhs = float((Ax * torch.from_numpy(fbar).to(dev).double()).sum())
+    rhs = float((x.double() * torch.from_numpy(got).to(dev).double()).sum())
+    dot = abs(lhs - rhs) / (float(Ax.norm()) * float(np.linalg.norm(fbar)))
+    print(f"[parity] {name} adjoint: vs oracle rel-L2 {rel:.3e}, dot product {dot:.3e}",
+          flush=True)
+    assert rel <= REL_L2 and dot <= 1e-5
+
+
+def test_recon_parity_config1_with_helix_offsets():
+    """The 64^3 parity workload on a helix with lambda0 = 0.7 rad, z0 = -13.2 mm and the first
+    view at 0.31 rad (the grid follows the helix's mid-height)."""
+    wl = configs.with_helix_offsets(configs.config1())
+    _recon_parity("config1 offsets", wl.geom.as_dict(), wl.grid.as_dict(), wl.phantom, wl.seed)
+
+
+def test_adjoint_parity_with_helix_offsets():
+    wl = configs.with_helix_offsets(
+        configs.tiny(nxy=12, nz=20, cols=40, rows=8, views_per_turn=60, turns=4, feed=24.0,
+                     dxy=2.5, slices_per_pitch=8), lambda0=-2.1, z0=7.7, lambda_first=-0.45)
+    _adjoint_parity("offsets", wl.geom.as_dict(), wl.grid.as_dict(), 31)
+
+
+def test_device_plan_with_helix_offsets():
+    """The GPU PI-line solve on the offset helix: the same tables as the host plan."""
+    _dev()
+    wl = configs.with_helix_offsets(configs.config1())
+    g, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    host = K.Plan(g, gr, bind=False)
+    gpu = K.Plan(g, gr, bind=False, gpu_plan=True, device=0)
+    for key in ("first_view", "last_view", "n_vv", "n_valid_voxels", "window_views", "window_lo"):
+        assert host.info[key] == gpu.info[key], key
+    for t in ("pi_nfirst", "pi_nlast", "fov", "valid"):
+        assert np.array_equal(host.export(t), gpu.export(t)), t
+    for t in ("pi_li", "pi_lo"):
+        d = np.abs(host.export(t) - gpu.export(t)).max()
+        print(f"[plan] offsets: max |{t} host - gpu| = {d:.3e} views", flush=True)
+        assert d <= 1e-9
+
+
+def _non_commensurate():
+    """dz = 1.7 mm against a 24 mm feed: 24 / 1.7 is not an integer, so slices do not repeat
+    from pitch to pitch and the plan solves the PI lines of every slice (one table pitch
+    holding the whole grid)."""
+    wl = configs.tiny(nxy=20, nz=30, cols=48, rows=8, views_per_turn=72, turns=5, feed=24.0,
+                      dxy=2.0, slices_per_pitch=12)
+    geom = wl.geom.as_dict()
+    gr = configs.centred_grid(wl.geom, 20, 20, 30, 2.0, 1.7).as_dict()
+    return wl, geom, gr
+
+
+def test_recon_parity_non_commensurate_grid():
+    wl, geom, gr = _non_commensurate()
+    plan = _recon_parity("non-commensurate dz 1.7", geom, gr, wl.phantom, wl.seed)
+    assert plan.info["commensurate"] == 0 and plan.info["n_pitches"] == 1
+
+
+def test_adjoint_parity_non_commensurate_grid():
+    wl, geom, gr = _non_commensurate()
+    gr = dict(gr, nx=12, ny=12, x_first=-11.0, y_first=-11.0, nz=16)
+    _adjoint_parity("non-commensurate dz 1.7", geom, gr, 33)

@@ -14,9 +14,21 @@ import oracle as O
 from synth import configs, phantom
 
 
-def _scan(**kw):
+# Helix offsets of Sec. II (lambda0: angle of the source at lambda = 0, z0: its height) and a
+# first view that is not a multiple of the view step; the geometric pins run with and
+# without them, so that a dropped or mis-signed offset anywhere fails one of them.
+OFFSETS = {"lambda0": 0.7, "z0": -13.2, "lambda_first": 0.31}
+
+
+def _scan(offsets=False, **kw):
     wl = configs.tiny(**kw)
-    return O.Scan(wl.geom.as_dict()), wl
+    geom = wl.geom.as_dict()
+    if offsets:
+        geom.update(OFFSETS)
+    return O.Scan(geom), wl
+
+
+with_offsets = pytest.mark.parametrize("offsets", [False, True], ids=["no-offsets", "offsets"])
 
 
 # ---------------------------------------------------------------- phantom / projector
@@ -72,11 +84,12 @@ def test_gaussian_line_integral_vs_quadrature():
 
 
 # ---------------------------------------------------------------- geometry (v*, alpha*, w*)
-def test_backprojection_coordinates_vs_ray_cylinder_intersection():
+@with_offsets
+def test_backprojection_coordinates_vs_ray_cylinder_intersection(offsets):
     """alpha*, v*, w* of the backprojection step equal the detector cell hit by the ray
     source -> x, found by intersecting that ray with the curved detector (a cylinder of
     radius D about the source, axis parallel to z)."""
-    scan, _ = _scan()
+    scan, _ = _scan(offsets)
     rng = np.random.default_rng(2)
     for _ in range(50):
         x, y, z = rng.uniform(-30, 30), rng.uniform(-30, 30), rng.uniform(-20, 60)
@@ -95,10 +108,11 @@ def test_backprojection_coordinates_vs_ray_cylinder_intersection():
         assert abs(w - w_ref) < 1e-10
 
 
-def test_w_kappa_is_the_kappa_plane_on_the_detector():
+@with_offsets
+def test_w_kappa_is_the_kappa_plane_on_the_detector(offsets):
     """Points of the kappa-plane through a(l), a(l+psi), a(l+2psi), seen from a(l), land
     on the detector curve w = w_kappa(alpha, psi) (R_o = R, P = feed per turn)."""
-    scan, _ = _scan(feed=40.0)
+    scan, _ = _scan(offsets, feed=40.0)
     rng = np.random.default_rng(3)
     lam = 0.7
     b = lam + scan.lambda0
@@ -119,8 +133,9 @@ def test_w_kappa_is_the_kappa_plane_on_the_detector():
 
 
 # ---------------------------------------------------------------- PI lines
-def test_pi_line_axis_closed_form():
-    scan, _ = _scan()
+@with_offsets
+def test_pi_line_axis_closed_form(offsets):
+    scan, _ = _scan(offsets)
     z = np.array([-10.0, 0.0, 7.3, 55.0])
     li, lo = O.pi_line(scan, np.zeros(4), np.zeros(4), z)
     ref = (z - scan.z0) / scan.h - math.pi / 2
@@ -128,8 +143,9 @@ def test_pi_line_axis_closed_form():
     assert np.allclose(lo, ref + math.pi, atol=1e-12, rtol=0)
 
 
-def test_pi_line_chord_contains_point_and_spans():
-    scan, _ = _scan(feed=60.0)
+@with_offsets
+def test_pi_line_chord_contains_point_and_spans(offsets):
+    scan, _ = _scan(offsets, feed=60.0)
     rng = np.random.default_rng(4)
     x = rng.uniform(-150, 150, 400)
     y = rng.uniform(-150, 150, 400)
@@ -151,9 +167,10 @@ def test_pi_line_chord_contains_point_and_spans():
     assert (span <= math.pi + 2 * np.arcsin(rho / scan.R) + 1e-12).all()
 
 
-def test_pi_line_periodicity():
+@with_offsets
+def test_pi_line_periodicity(offsets):
     """lambda_{i,o}(x, y, z + kP) = lambda_{i,o}(x, y, z) + 2 k pi  (Sec. II periodicity)."""
-    scan, _ = _scan(feed=50.0)
+    scan, _ = _scan(offsets, feed=50.0)
     rng = np.random.default_rng(5)
     x, y, z = rng.uniform(-100, 100, (3, 200))
     li0, lo0 = O.pi_line(scan, x, y, z)
@@ -163,12 +180,13 @@ def test_pi_line_periodicity():
         assert np.abs(lo - lo0 - 2 * math.pi * k).max() < 1e-11
 
 
-def test_pi_endpoints_project_on_tam_danielsson_boundaries():
+@with_offsets
+def test_pi_endpoints_project_on_tam_danielsson_boundaries(offsets):
     """Seen from a(lambda_i), x projects on the upper TD boundary
     w_top(alpha) = (D P / 2pi R)(pi/2 - alpha)/cos(alpha); from a(lambda_o) on the lower one
     w_bot(alpha) = -(D P / 2pi R)(pi/2 + alpha)/cos(alpha) (closed form for the curved
     detector, derived from the projection of the adjacent helix turns)."""
-    scan, _ = _scan(feed=70.0)
+    scan, _ = _scan(offsets, feed=70.0)
     rng = np.random.default_rng(6)
     x, y, z = rng.uniform(-120, 120, 100), rng.uniform(-120, 120, 100), rng.uniform(0, 80, 100)
     li, lo = O.pi_line(scan, x, y, z)
@@ -409,6 +427,81 @@ def test_sinogram_shift_by_one_turn_shifts_volume_by_one_pitch():
     both = v[:-ns] & vs[ns:]
     assert both.any()
     assert np.abs(fs[ns:][both] - f[:-ns][both]).max() <= 1e-10 * np.abs(f).max()
+
+
+# ---------------------------------------------------------------- helix offsets (Sec. II)
+def _offset_case(**over):
+    wl = configs.tiny(nxy=14, nz=16, cols=48, rows=8, views_per_turn=72, turns=4, feed=24.0,
+                      dxy=2.0, slices_per_pitch=12)
+    geom = dict(wl.geom.as_dict(), **OFFSETS)
+    geom.update(over)
+    gr = configs.centred_grid(configs.Geometry(**geom), 14, 14, 16, 2.0, 2.0).as_dict()
+    rng = np.random.default_rng(21)
+    g = rng.normal(size=(geom["n_views"], geom["det_rows"], geom["det_cols"]))
+    return geom, gr, g
+
+
+def test_rotating_the_helix_rotates_the_volume():
+    """lambda0 -> lambda0 + pi/2 turns every source position by pi/2 about the axis, so the
+    same data describe the object turned by pi/2: the reconstruction at (x, y) equals the
+    first one at (y, -x).  On a square grid centred on the axis that is an index map, and
+    the discrete operator (v*, alpha*, w*, PI lines, coverage, validity) must follow it
+    exactly; a lambda0 dropped or mis-signed in any of them breaks it."""
+    geom, gr, g = _offset_case()
+    f0, v0 = O.recon(O.Scan(geom), gr, g)
+    f1, v1 = O.recon(O.Scan(dict(geom, lambda0=geom["lambda0"] + 0.5 * math.pi)), gr, g)
+    n = gr["nx"]
+    # f1[iz, iy, ix] is f0 at (x, y) = (y_iy, -x_ix): column iy, row n - 1 - ix
+    rot0 = np.transpose(f0[:, ::-1, :], (0, 2, 1))
+    rotv = np.transpose(v0[:, ::-1, :], (0, 2, 1))
+    assert np.array_equal(v1, rotv) and v1.sum() > 500
+    assert np.abs(f1 - rot0).max() <= 1e-9 * np.abs(f0).max()
+    # and the volume itself is not symmetric under that turn (the check has teeth)
+    assert np.abs(f0 - rot0)[v0 & rotv].max() > 0.1 * np.abs(f0).max()
+
+
+def test_raising_the_helix_raises_the_volume():
+    """z0 -> z0 + 3 dz lifts every source position by three slices, so the same data describe
+    the object lifted by 3 dz: slice iz of the new reconstruction equals slice iz - 3 of the
+    first wherever both are valid."""
+    geom, gr, g = _offset_case()
+    k = 3
+    f0, v0 = O.recon(O.Scan(geom), gr, g)
+    f1, v1 = O.recon(O.Scan(dict(geom, z0=geom["z0"] + k * gr["dz"])), gr, g)
+    both = v1[k:] & v0[:-k]
+    assert both.sum() > 500
+    assert np.array_equal(v1[k:][both], v0[:-k][both])
+    assert np.abs(f1[k:] - f0[:-k])[both].max() <= 1e-9 * np.abs(f0).max()
+    assert np.abs(f1 - f0)[v0 & v1].max() > 0.1 * np.abs(f0).max()
+
+
+def test_pitch_by_pitch_equals_whole_scan_with_offsets():
+    """The periodicity of Sec. II (tables of the first pitch reused with lambda + 2 k pi) holds
+    for any lambda0, z0 and first view angle."""
+    geom, gr, g = _offset_case()
+    scan = O.Scan(geom)
+    tab = O.pitch_tables(scan, gr)
+    assert tab["pitches"].n_pitches >= 2
+    fp, vp = O.recon(scan, gr, g, mode="pitch", tables=tab)
+    fw, vw = O.recon(scan, gr, g, mode="whole")
+    assert np.array_equal(vp, vw) and vp.any()
+    assert np.abs(fp - fw).max() <= 1e-10 * np.abs(fw).max()
+
+
+def test_ball_reconstructs_with_helix_offsets():
+    """A uniform ball seen by a helix with lambda0, z0 and a first view off the view grid
+    (data from the closed-form projector, which places the source independently)
+    reconstructs to +1 inside."""
+    wl = configs.tiny(nxy=24, nz=12, cols=64, rows=8, views_per_turn=90)
+    geom = dict(wl.geom.as_dict(), **OFFSETS)
+    gr = configs.centred_grid(configs.Geometry(**geom), 24, 24, 12, 2.0, 2.0).as_dict()
+    zc = gr["z_first"] + 0.5 * (gr["nz"] - 1) * gr["dz"]
+    ph = {"kind": "ellipsoids", "centre": np.array([[0, 0, zc]]), "axes": np.array([[15.0] * 3]),
+          "rot": np.array([np.eye(3)]), "density": np.array([1.0])}
+    f, valid = O.recon(O.Scan(geom), gr, phantom.project(ph, geom))
+    c = gr["nz"] // 2
+    assert valid[c, 9:15, 9:15].all()
+    assert np.abs(f[c, 9:15, 9:15] - 1.0).max() < 0.02
 
 
 # ---------------------------------------------------------------- adjoint

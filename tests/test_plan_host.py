@@ -212,3 +212,22 @@ def test_non_commensurate_grid_is_one_pitch():
     p = pk.Plan(wl.geom.as_dict(), gr, bind=False)
     assert p.info["commensurate"] == 0 and p.info["n_pitches"] == 1
     assert p.info["slices_per_pitch"] == 10
+
+
+def test_tables_bit_exact_with_helix_offsets():
+    """lambda0, z0 and a first view off the view grid (Sec. II helix): PI tables, validity
+    and the pitch window against the oracle, integer tables bit for bit."""
+    wl = configs.with_helix_offsets(configs.config1())
+    p, scan = _compare_tables(wl)
+    gr = wl.grid.as_dict()
+    tab = O.pitch_tables(scan, gr)
+    assert p.info["window_lo"] == tab["n_lo"]
+    assert p.info["window_views"] == tab["n_hi"] - tab["n_lo"] + 1
+    assert p.info["n_vv"] == O.n_voxel_views(scan, gr, tab)
+    f_valid = np.zeros((gr["nz"], gr["ny"], gr["nx"]), bool)
+    pit = tab["pitches"]
+    for k in range(pit.n_pitches):
+        sl, js = pit.slices(k)
+        s = k * scan.Nv
+        f_valid[sl] = O.valid_mask(scan, tab["nf"][js] + s, tab["nl"][js] + s, tab["fov"][js])
+    assert np.array_equal(p.export("valid").astype(bool), f_valid) and f_valid.sum() > 1000
