@@ -259,6 +259,22 @@ int katsevich_add_noise(const float *d_in, float *d_out, uint64_t n, const float
 int katsevich_rmse_ssim(const float *d_f, const float *d_ref, uint64_t n, double *d_result,
                         void *d_scratch, uint64_t scratch_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): katsevich_rmse_ssim with the same
+ * kernels and result, its reduction partials kept in a library-owned static device array
+ * of KATS_STATIC_SCRATCH_BYTES instead of a caller scratch buffer.  Each GPU holds its own
+ * copy of the array until the process ends; its address is looked up on the first call
+ * on a device (with that device current), and the call allocates nothing.  The reduction
+ * needs the same fixed scratch for any n, so no n >= 1 is too large; a library whose
+ * static array were smaller than that need would return KATS_EWORKSPACE.  Nothing in the
+ * array needs clearing (every launch writes the partials it reads), but every call on one
+ * GPU shares it: calls that overlap on one GPU (other streams, other threads) race and
+ * must be serialised by the caller.  Errors: KATS_EINVAL (null pointer, n < 1),
+ * KATS_EWORKSPACE, KATS_EHIP. */
+#define KATS_STATIC_SCRATCH_BYTES 164096
+int katsevich_rmse_ssim_noscratch(const float *d_f, const float *d_ref, uint64_t n, double *d_result,
+                                  void *stream);
+
 /* Free a plan (NULL is ignored).  Device buffers stay with the caller. */
 void katsevich_plan_destroy(katsevich_plan_t plan);
 

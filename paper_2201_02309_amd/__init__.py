@@ -6,8 +6,10 @@ that library's sources (``csrc/``), its build step and a thin ctypes binding.
 """
 from .katsevich import (Plan, KatsevichError, recon, recon_backward, filter_views,
                         backproject, backproject_batch, filtered_shape, KatsevichFn,
-                        load_library, TABLES, sparse_upsample, max_value, add_noise, rmse_ssim)
+                        load_library, TABLES, sparse_upsample, max_value, add_noise, rmse_ssim,
+                        rmse_ssim_noscratch)
 
 __all__ = ["Plan", "KatsevichError", "recon", "recon_backward", "filter_views", "backproject",
            "backproject_batch", "filtered_shape", "KatsevichFn", "load_library", "TABLES",
-           "sparse_upsample", "max_value", "add_noise", "rmse_ssim"]
+           "sparse_upsample", "max_value", "add_noise", "rmse_ssim",
+           "rmse_ssim_noscratch"]

@@ -403,6 +403,25 @@ int katsevich_rmse_ssim(const float *d_f, const float *d_ref, uint64_t n, double
     return KATS_OK;
 }
 
+int katsevich_rmse_ssim_noscratch(const float *d_f, const float *d_ref, uint64_t n, double *d_result,
+                                  void *stream) {
+    g_err.clear();
+    if (!d_f || !d_ref || !d_result || n < 1)
+        return fail(KATS_EINVAL, "katsevich_rmse_ssim_noscratch: null pointer or n < 1");
+    void *scr = nullptr;
+    uint64_t scr_bytes = 0;
+    hipError_t e = kats::static_scratch(&scr, &scr_bytes);
+    if (e != hipSuccess) return hip_fail(e, "katsevich_rmse_ssim_noscratch: static scratch address");
+    if (scr_bytes < kats::data_scratch_bytes())
+        return fail(KATS_EWORKSPACE, "katsevich_rmse_ssim_noscratch: reduction needs " +
+                                         std::to_string(kats::data_scratch_bytes()) +
+                                         " bytes of scratch, the static array holds " +
+                                         std::to_string(scr_bytes));
+    e = kats::launch_rmse_ssim(d_f, d_ref, n, d_result, scr, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "katsevich_rmse_ssim_noscratch: launch");
+    return KATS_OK;
+}
+
 int katsevich_backproject_batch(const katsevich_plan_t *plans, const float *const *d_gF,
                                 float *const *d_vol, int n, void *stream) {
     g_err.clear();

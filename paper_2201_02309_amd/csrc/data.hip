@@ -16,8 +16,20 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.hpp"
+
+// Bytes of reduction scratch: 4096 block partials of 5 doubles, then 5 doubles of moments,
+// rounded up to 256 bytes.
+constexpr unsigned long long kDataScratchBytes = 4096ull * 5 * sizeof(double) + 256;
+
+// Library-owned reduction scratch for callers that cannot allocate device memory: one
+// copy per GPU (each device's code object holds its own), held until the process ends.
+// In host code this name is only a shadow of the device array, never its address:
+// kats::static_scratch() looks the address up once per device and returns it.
+static __device__ __align__(256) unsigned char scratch[kDataScratchBytes];
+static_assert(kDataScratchBytes == KATS_STATIC_SCRATCH_BYTES, "header size of the static scratch");
 
 namespace kats {
 
@@ -168,6 +180,8 @@ __global__ __launch_bounds__(kThreads) void k_noise(const float *__restrict__ in
 
 // ---------------------------------------------------------------- reductions
 constexpr int kRedBlocks = 4096;     // partials per reduction (5 doubles each in scratch)
+static_assert((unsigned long long)kRedBlocks * 5 * sizeof(double) + 5 * sizeof(double) <= kDataScratchBytes,
+              "reduction scratch too small");
 
 __device__ inline double block_sum(double v, double *sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -306,7 +320,31 @@ int red_blocks(unsigned long long n) {
 
 }  // namespace
 
-uint64_t data_scratch_bytes() { return (uint64_t)kRedBlocks * 5 * sizeof(double) + 256; }
+uint64_t data_scratch_bytes() { return kDataScratchBytes; }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void **out, uint64_t *bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {                      // first call on this device, device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    *bytes = sizeof(scratch);
+    return hipSuccess;
+}
 
 hipError_t launch_upsample(const float *sp, float *full, long long lines, int cols, int ns, int step,
                            hipStream_t s) {

@@ -57,6 +57,9 @@ hipError_t launch_noise(const float *in, float *out, unsigned long long n, const
                         float sd_e, uint64_t seed, hipStream_t s);
 hipError_t launch_rmse_ssim(const float *f, const float *g, unsigned long long n, double *result,
                             void *scratch, hipStream_t s);
+// Device address (for the current device) and size of the library-owned static reduction
+// scratch; the address is looked up with hipGetSymbolAddress on a device's first call.
+hipError_t static_scratch(void **out, uint64_t *bytes);
 
 // PI lines (lambda_i, lambda_o) of every voxel of the first n_tab slices, float64, into
 // d_li / d_lo [n_tab][ny][nx].

@@ -71,7 +71,7 @@ EXPORTED = ["katsevich_plan", "katsevich_plan_query", "katsevich_plan_bind",
             "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error",
             "katsevich_plan_device", "katsevich_plan_device_scratch_bytes",
             "katsevich_sparse_upsample", "katsevich_data_scratch_bytes", "katsevich_max",
-            "katsevich_add_noise", "katsevich_rmse_ssim"]
+            "katsevich_add_noise", "katsevich_rmse_ssim", "katsevich_rmse_ssim_noscratch"]
 
 _lib = None
 
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.katsevich_rmse_ssim.argtypes = [c_void_p, c_void_p, c_uint64, c_void_p, c_void_p, c_uint64,
                                         c_void_p]
     lib.katsevich_rmse_ssim.restype = c_int
+    lib.katsevich_rmse_ssim_noscratch.argtypes = [c_void_p, c_void_p, c_uint64, c_void_p, c_void_p]
+    lib.katsevich_rmse_ssim_noscratch.restype = c_int
     lib.katsevich_plan_destroy.argtypes = [c_void_p]
     lib.katsevich_plan_destroy.restype = None
     lib.katsevich_status_string.argtypes = [c_int]
@@ -432,6 +434,22 @@ def rmse_ssim(f, ref, scratch=None, result=None):
                                         c_uint64(f.numel()), c_void_p(result.data_ptr()),
                                         c_void_p(scratch.data_ptr()), c_uint64(scratch.numel()),
                                         _stream_handle(f.device)))
+    return result
+
+
+def rmse_ssim_noscratch(f, ref, result=None):
+    """katsevich_rmse_ssim_noscratch: as rmse_ssim, with the library's static device scratch
+    (no scratch buffer; calls overlapping on one GPU race)."""
+    import torch
+    _f32(f, "f")
+    _f32(ref, "ref")
+    if f.shape != ref.shape:
+        raise KatsevichError(-3, "f and ref differ in shape")
+    result = torch.empty(2, dtype=torch.float64, device=f.device) if result is None else result
+    lib = load_library()
+    _check(lib, lib.katsevich_rmse_ssim_noscratch(c_void_p(f.data_ptr()), c_void_p(ref.data_ptr()),
+                                                  c_uint64(f.numel()), c_void_p(result.data_ptr()),
+                                                  _stream_handle(f.device)))
     return result
 
 
