@@ -150,31 +150,54 @@ enum {
 int katsevich_plan(const katsevich_geometry *geom, const katsevich_grid *grid,
                    const katsevich_options *opts, katsevich_plan_t *out);
 
-/* Device scratch (bytes) katsevich_plan_device needs: two float64 per voxel of one
- * pitch's slices (n_table_slices x ny x nx), 256-byte aligned halves. */
-uint64_t katsevich_plan_device_scratch_bytes(const katsevich_geometry *geom,
-                                             const katsevich_grid *grid);
+/* Buffers of katsevich_plan_device for a geometry, grid and options.  scratch_bytes: device
+ * scratch, free again when the call returns; on return it holds the table pitch's PI
+ * tables (each [n_table_slices][ny][nx]): float64 lambda_i and lambda_o in view units at
+ * pi_li_offset / pi_lo_offset, int32 first / last covered view at pi_nfirst_offset /
+ * pi_nlast_offset, uint8 field-of-view flags at fov_offset.  table_bytes: the device table
+ * buffer, laid out for an upper bound of the pitch window (it may exceed the table_bytes
+ * of the same plan built on the host). */
+typedef struct katsevich_device_plan_sizes {
+    uint64_t scratch_bytes, table_bytes;
+    uint64_t pi_li_offset, pi_lo_offset, pi_nfirst_offset, pi_nlast_offset, fov_offset;
+    int32_t n_table_slices, reserved;
+} katsevich_device_plan_sizes;
 
-/* Same plan as katsevich_plan (same tables up to the last bits of the float64 PI limits),
- * with the PI lines of every voxel of one pitch (pre-calculating step 2 of Sec. II, the
- * plan's dominant cost) solved on the GPU in float64; everything else is built on the host.
- * d_scratch: caller device buffer of katsevich_plan_device_scratch_bytes() bytes (256-byte
- * aligned), free again when the call returns; the call synchronises stream.  Errors as
- * katsevich_plan, plus KATS_EWORKSPACE (scratch too small) and KATS_EHIP. */
+/* Errors: KATS_EINVAL, KATS_EINVAL_GEOMETRY (as katsevich_plan's validation). */
+int katsevich_plan_device_sizes(const katsevich_geometry *geom, const katsevich_grid *grid,
+                                const katsevich_options *opts, katsevich_device_plan_sizes *out);
+
+/* The plan of katsevich_plan built on the GPU in float64 (pre-calculating step of Sec. II),
+ * every table written by kernels straight into the caller's table buffer d_tables (>=
+ * table_bytes of katsevich_plan_device_sizes, 256-byte aligned), to which the returned plan
+ * is bound (katsevich_plan_bind then moves the tables device to device).  The rebinning
+ * tables, psi_hat, the Hilbert spectrum, the per-view trigonometry and the footprint boxes
+ * follow the host builder's float64 arithmetic term for term; the PI lines are solved per
+ * voxel by Newton's method on the chord's angle, projected onto [-pi, pi] at every step,
+ * safeguarded by bisection (the lines of pre-calculating step 2).  Integer tables equal
+ * the host plan's; float tables agree to the last bits of the libm functions.  d_scratch:
+ * scratch_bytes, 256-byte aligned.  Enqueued on stream, which the call synchronises once
+ * at the end to read back the plan's counts.  Errors as katsevich_plan, plus
+ * KATS_EWORKSPACE (scratch too small), KATS_ESHAPE (table buffer too small), KATS_EHIP. */
 int katsevich_plan_device(const katsevich_geometry *geom, const katsevich_grid *grid,
                           const katsevich_options *opts, void *d_scratch, uint64_t scratch_bytes,
-                          void *stream, katsevich_plan_t *out);
+                          void *d_tables, uint64_t table_bytes, void *stream, katsevich_plan_t *out);
 
 /* Sizes and counts of the plan. */
 int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out);
 
 /* Copy the plan's device tables (table_bytes bytes) into caller-owned device memory
  * d_tables (256-byte aligned) on stream, then wait for that copy.  The buffer must stay
- * alive and unchanged while the plan is used.  May be called again to rebind. */
+ * alive and unchanged while the plan is used.  May be called again to rebind (a plan built
+ * by katsevich_plan_device copies from the buffer it is bound to; binding that same buffer
+ * again does nothing). */
 int katsevich_plan_bind(katsevich_plan_t plan, void *d_tables, uint64_t bytes, void *stream);
 
 /* Copy one host table (KATS_TABLE_*) into host_dst of exactly the table's size in bytes
- * (KATS_ESHAPE otherwise).  Used by tests to compare integer tables bit for bit. */
+ * (KATS_ESHAPE otherwise).  Used by tests to compare integer tables bit for bit.  A plan
+ * built by katsevich_plan_device exports the rebinning tables and the validity mask (read
+ * back from its device PI table); its PI tables themselves are KATS_EINVAL here (they are
+ * in the scratch of the build on return). */
 int katsevich_plan_export(katsevich_plan_t plan, int which, void *host_dst, uint64_t bytes);
 
 /* Reconstruct: d_sino float32 [n_views][rows][cols] -> d_vol float32 [nz][ny][nx].

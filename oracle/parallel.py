@@ -171,15 +171,24 @@ def _bp_slice(geom, grid, fspec, a, k, iz, j, li, lo, nf, nl, m):
     return iz, vals
 
 
-def recon(geom: dict, grid: dict, g, workers: int | None = None, tables=None):
+def warm(_=None) -> int:
+    """A no-op task: submitting one per worker starts every worker process (interpreter and
+    imports) before a timed region."""
+    return os.getpid()
+
+
+def recon(geom: dict, grid: dict, g, workers: int | None = None, tables=None, ex=None):
     """katsevich_oracle.recon(mode="pitch") with the PI lines, the filtering of each pitch
-    window and the backprojection of each slice spread over worker processes."""
+    window and the backprojection of each slice spread over worker processes (those of the
+    executor ex when given)."""
     scan = O.Scan(geom)
     g = np.asarray(g)
     nx, ny, nz = int(grid["nx"]), int(grid["ny"]), int(grid["nz"])
     f = np.zeros((nz, ny, nx))
     valid = np.zeros((nz, ny, nx), dtype=bool)
-    with pool(workers or default_workers()) as ex:
+    own = ex is None
+    ex = ex or pool(workers or default_workers())
+    try:
         tab = tables or pitch_tables(geom, grid, ex=ex)
         pit = tab["pitches"]
         for k in range(pit.n_pitches):
@@ -211,6 +220,9 @@ def recon(geom: dict, grid: dict, g, workers: int | None = None, tables=None):
                     f[iz][valid[iz]] = vals
             finally:
                 fs.close()
+    finally:
+        if own:
+            ex.shutdown()
     return f, valid
 
 

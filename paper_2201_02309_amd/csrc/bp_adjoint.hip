@@ -45,11 +45,24 @@ struct BpTShared {
 
 // FB: some box of the plan may exceed the LDS tile; those views scatter their taps
 // straight into g^F-bar with global atomics (the cells the forward's HBM path reads).
-template <int KZ, bool FB, bool P4>
+//
+// Column coordinate.  The cotangent scattered here is arbitrary (random in the dot-product
+// and oracle tests, a residual in training), so the bilinear weights themselves must be
+// accurate, not only the interpolated value: a column coordinate formed in float32 at the
+// detector's scale (|alpha*/dalpha| up to ~370 cells, ulp 3e-5) plus the float32 rounding
+// of u, v from coordinates of ~180 mm moves the weights by ~3e-5, which is what a random
+// cotangent sees.  Each lane therefore measures its angle from the ray to its tile's centre
+// (TileRay, float64 from the plan): with small in-tile offsets (du, dv) of (u, v),
+//     alpha* - alpha_c = atan2(du v_c - u_c dv, rho_c^2 + u_c du + v_c dv),
+// an angle of a few cells whose float32 error is ~1e-6 cell, and atan of its small tangent
+// is the odd series through t^11 (remainder below t^13/13: ~1e-17 at the tangents of
+// voxels in the field of view).
+template <int KZ, bool FB>
 __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *__restrict__ gFbar,
                          int rows, int cols, long long first_view,
                          const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
-                         int bxi, int byi, int bz, BpTShared<KZ> &S) {
+                         const float4 *__restrict__ ray_tab, int bxi, int byi, int bz,
+                         BpTShared<KZ> &S) {
     static_assert(KZ % kKG == 0 && KZ / kKG <= 8, "groups use 8-bit masks");
     constexpr int kLR = lds_rows<KZ>();
     constexpr int NG = KZ / kKG;
@@ -135,11 +148,13 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     }
     __syncthreads();
 
-    const float x = fmaf((float)ix, p.dx, p.x_first);
-    const float y = fmaf((float)iy, p.dy, p.y_first);
+    // offsets from the tile centre (half-integers of the grid steps)
+    const float ddx = ((float)(tid & (kT - 1)) - 0.5f * (kT - 1)) * p.dx;
+    const float ddy = ((float)(tid >> 4) - 0.5f * (kT - 1)) * p.dy;
     const float zoff = (float)j0 * p.dz;
     const uint2 *__restrict__ boxes =
         box_tab + ((size_t)(run * p.tiles_y + byi) * p.tiles_x + bxi) * p.W;
+    const float4 *__restrict__ rays = ray_tab + ((size_t)byi * p.tiles_x + bxi) * p.W;
     const size_t vstride = (size_t)rows * cols;
     auto fits = [](const BpBox &b) { return !FB || (b.nr <= kLR && b.nc <= kLPT); };
     // flush of view m's box from buffer buf: lanes over 4 rows x 64 columns per pass
@@ -163,23 +178,22 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         const int buf = (m - mlo) & 1;
         const BpBox b = unpack_box(ldg(boxes + m));
         const float4 vt = ldg(view_tab + m);
-        const float u = fmaf(-x, vt.y, y * vt.x);
-        const float v = p.R - fmaf(x, vt.x, y * vt.y);
+        const float4 ray = ldg(rays + m);          // col, u_c, v_c, rho_c^2
+        const float du = fmaf(-ddx, vt.y, ddy * vt.x);
+        const float dv = -fmaf(ddx, vt.x, ddy * vt.y);
+        const float u = ray.y + du, v = ray.z + dv;
         const float vinv = __builtin_amdgcn_rcpf(v);
         const float rinv = __builtin_amdgcn_rsqf(fmaf(u, u, v * v));
-        float acol;
-        if (P4 || p.atan_deg >= 0) {
-            const float t = u * vinv;
-            const float s2 = t * t;
-            constexpr int deg = P4 ? 4 : 8;
-            float qa = p.atan_coef[deg];
-#pragma unroll
-            for (int k = deg - 1; k >= 0; --k) qa = fmaf(qa, s2, p.atan_coef[k]);
-            acol = t * qa;
-        } else {
-            acol = atan2f(u, v) * p.inv_dalpha;
-        }
-        const float cc = med3(acol + (p.col_c - (float)b.c0), 0.0f, (float)(b.nc - 2));
+        const float tn = fmaf(du, ray.z, -ray.y * dv);
+        const float td = fmaf(ray.y, du, fmaf(ray.z, dv, ray.w));
+        const float t = tn * __builtin_amdgcn_rcpf(td);
+        const float s2 = t * t;
+        float qa = fmaf(s2, -1.0f / 11.0f, 1.0f / 9.0f);
+        qa = fmaf(qa, s2, -1.0f / 7.0f);
+        qa = fmaf(qa, s2, 1.0f / 5.0f);
+        qa = fmaf(qa, s2, -1.0f / 3.0f);
+        qa = fmaf(qa, s2, 1.0f);
+        const float cc = med3(fmaf(t * qa, p.inv_dalpha, ray.x), 0.0f, (float)(b.nc - 2));
         const int c0 = (int)cc;
         const float tc = cc - (float)c0;
         const float q = p.q_scale * rinv;
@@ -254,26 +268,27 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     if (mlo <= mhi && fits(prev_b)) flush(mhi, prev_b, (mhi - mlo) & 1);
 }
 
-template <int KZ, bool FB, bool P4>
+template <int KZ, bool FB>
 __global__ __launch_bounds__(kNT) void k_bpT_lds(BpArgs p, const float *__restrict__ fvol,
                                                  float *__restrict__ gFbar, int rows, int cols,
                                                  long long first_view,
                                                  const float4 *__restrict__ view_tab,
-                                                 const uint2 *__restrict__ box_tab) {
+                                                 const uint2 *__restrict__ box_tab,
+                                                 const float4 *__restrict__ ray_tab) {
     __shared__ BpTShared<KZ> S;
-    bpT_tile<KZ, FB, P4>(p, fvol, gFbar, rows, cols, first_view, view_tab, box_tab, blockIdx.x,
-                         blockIdx.y, blockIdx.z, S);
+    bpT_tile<KZ, FB>(p, fvol, gFbar, rows, cols, first_view, view_tab, box_tab, ray_tab, blockIdx.x,
+                     blockIdx.y, blockIdx.z, S);
 }
 
 template <int KZ>
-void launch_bpT(int cls, dim3 grid, hipStream_t s, const BpArgs &a, const float *gvol, float *gFbar,
-                int rows, int cols, long long first_view, const float4 *view, const uint2 *boxes) {
-    switch (cls) {      // bit 0: HBM path for boxes beyond the LDS tile, bit 1: short atan polynomial
-        case 0: hipLaunchKernelGGL((k_bpT_lds<KZ, false, false>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
-        case 1: hipLaunchKernelGGL((k_bpT_lds<KZ, true, false>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
-        case 2: hipLaunchKernelGGL((k_bpT_lds<KZ, false, true>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
-        default: hipLaunchKernelGGL((k_bpT_lds<KZ, true, true>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes); break;
-    }
+void launch_bpT(bool fb, dim3 grid, hipStream_t s, const BpArgs &a, const float *gvol, float *gFbar,
+                int rows, int cols, long long first_view, const float4 *view, const uint2 *boxes,
+                const float4 *rays) {
+    // fb: HBM path for boxes beyond the LDS tile
+    if (fb)
+        hipLaunchKernelGGL((k_bpT_lds<KZ, true>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes, rays);
+    else
+        hipLaunchKernelGGL((k_bpT_lds<KZ, false>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes, rays);
 }
 
 }  // namespace
@@ -282,11 +297,12 @@ hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFba
     const dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
     const BpArgs a = bp_args(k);
     const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
-    const int cls = (k.bp_all_fit ? 0 : 1) | ((k.atan_deg >= 0 && k.atan_deg <= 4) ? 2 : 0);
+    const float4 *rays = reinterpret_cast<const float4 *>(k.tref);
+    const bool fb = !k.bp_all_fit;
     switch (k.bp_kz) {
-        case 8: launch_bpT<8>(cls, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes); break;
-        case 32: launch_bpT<32>(cls, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes); break;
-        default: launch_bpT<16>(cls, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes); break;
+        case 8: launch_bpT<8>(fb, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        case 32: launch_bpT<32>(fb, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        default: launch_bpT<16>(fb, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
     }
     return hipGetLastError();
 }

@@ -89,6 +89,7 @@ KParams make_params(const PlanHost &P) {
     k.hil_im = reinterpret_cast<const float *>(base + L.hil_im);
     k.pi = reinterpret_cast<const PiEntry *>(base + L.pi);
     k.boxes = reinterpret_cast<const BpBox *>(base + L.boxes);
+    k.tref = reinterpret_cast<const TileRay *>(base + L.tref);
     k.bp_tiles_x = P.bp_tiles_x;
     k.bp_tiles_y = P.bp_tiles_y;
     k.bp_runs = P.bp_runs;
@@ -151,29 +152,53 @@ int katsevich_plan(const katsevich_geometry *geom, const katsevich_grid *grid,
     return KATS_OK;
 }
 
-uint64_t katsevich_plan_device_scratch_bytes(const katsevich_geometry *geom,
-                                             const katsevich_grid *grid) {
-    if (!geom || !grid) return 0;
-    return kats::pi_scratch_bytes(*geom, *grid);
+int katsevich_plan_device_sizes(const katsevich_geometry *geom, const katsevich_grid *grid,
+                                const katsevich_options *opts, katsevich_device_plan_sizes *out) {
+    g_err.clear();
+    if (!geom || !grid || !out) return fail(KATS_EINVAL, "katsevich_plan_device_sizes: null argument");
+    katsevich_options o{};
+    if (opts) o = *opts;
+    katsevich_device_plan_sizes z{};
+    std::string err;
+    uint64_t off[5] = {0, 0, 0, 0, 0};
+    int n_tab = 0;
+    int st;
+    try {
+        st = kats::device_plan_sizes(*geom, *grid, o, z.scratch_bytes, z.table_bytes, err);
+        if (st == KATS_OK) st = kats::device_plan_scratch_offsets(*geom, *grid, o, off, n_tab, err);
+    } catch (const std::bad_alloc &) {
+        st = KATS_ENOMEM;
+        err = "out of host memory";
+    }
+    if (st != KATS_OK) return fail(st, "katsevich_plan_device_sizes: " + err);
+    z.pi_li_offset = off[0];
+    z.pi_lo_offset = off[1];
+    z.pi_nfirst_offset = off[2];
+    z.pi_nlast_offset = off[3];
+    z.fov_offset = off[4];
+    z.n_table_slices = n_tab;
+    *out = z;
+    return KATS_OK;
 }
 
 int katsevich_plan_device(const katsevich_geometry *geom, const katsevich_grid *grid,
                           const katsevich_options *opts, void *d_scratch, uint64_t scratch_bytes,
-                          void *stream, katsevich_plan_t *out) {
+                          void *d_tables, uint64_t table_bytes, void *stream, katsevich_plan_t *out) {
     g_err.clear();
-    if (!geom || !grid || !out || !d_scratch)
+    if (!geom || !grid || !out || !d_scratch || !d_tables)
         return fail(KATS_EINVAL, "katsevich_plan_device: null argument");
     *out = nullptr;
-    if (!aligned256(d_scratch)) return fail(KATS_EINVAL, "katsevich_plan_device: scratch not 256-byte aligned");
+    if (!aligned256(d_scratch) || !aligned256(d_tables))
+        return fail(KATS_EINVAL, "katsevich_plan_device: scratch or table buffer not 256-byte aligned");
     katsevich_options o{};
     if (opts) o = *opts;
     katsevich_plan_s *p = new (std::nothrow) katsevich_plan_s();
     if (!p) return fail(KATS_ENOMEM, "katsevich_plan_device: out of host memory");
-    const kats::DevicePiSolve dev{d_scratch, scratch_bytes, stream};
+    const kats::DevicePlanBuffers buf{d_scratch, scratch_bytes, d_tables, table_bytes, stream};
     std::string err;
     int st;
     try {
-        st = kats::build_plan(*geom, *grid, o, p->P, err, &dev);
+        st = kats::build_plan_device(*geom, *grid, o, p->P, err, buf);
     } catch (const std::bad_alloc &) {
         st = KATS_ENOMEM;
         err = "out of host memory while planning";
@@ -229,7 +254,11 @@ int katsevich_plan_bind(katsevich_plan_t plan, void *d_tables, uint64_t bytes, v
         return fail(KATS_ESHAPE, "katsevich_plan_bind: table buffer smaller than table_bytes");
     if (!aligned256(d_tables)) return fail(KATS_EINVAL, "katsevich_plan_bind: buffer not 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(d_tables, P.image.data(), P.layout.total, hipMemcpyHostToDevice, s);
+    if (P.device_built && d_tables == P.d_tables) return KATS_OK;
+    // a device-built plan has no host image: its tables move from the buffer they were built in
+    hipError_t e = P.device_built
+        ? hipMemcpyAsync(d_tables, P.d_tables, P.layout.total, hipMemcpyDeviceToDevice, s)
+        : hipMemcpyAsync(d_tables, P.image.data(), P.layout.total, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "katsevich_plan_bind: hipMemcpyAsync");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "katsevich_plan_bind: hipStreamSynchronize");
@@ -244,6 +273,31 @@ int katsevich_plan_export(katsevich_plan_t plan, int which, void *host_dst, uint
     const void *src = nullptr;
     uint64_t n = 0;
     std::vector<uint8_t> valid;
+    if (P.device_built && which >= KATS_TABLE_PI_LI && which <= KATS_TABLE_FOV)
+        return fail(KATS_EINVAL, "katsevich_plan_export: a device-built plan keeps its PI tables on the "
+                                 "device (the scratch of katsevich_plan_device holds them on return)");
+    if (P.device_built && which == KATS_TABLE_VALID) {
+        // from the device PI table: entries relative to the window start, empty outside the FOV
+        const katsevich_grid &gr = P.grid;
+        const size_t plane = (size_t)gr.ny * gr.nx;
+        std::vector<kats::PiEntry> pe((size_t)P.n_tab * plane);
+        hipError_t e = hipMemcpy(pe.data(), static_cast<const unsigned char *>(P.d_tables) + P.layout.pi,
+                                 pe.size() * sizeof(kats::PiEntry), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "katsevich_plan_export: hipMemcpy");
+        const uint64_t need = (uint64_t)gr.nz * plane;
+        if (bytes != need) return fail(KATS_ESHAPE, "katsevich_plan_export: size mismatch (need " + std::to_string(need) + ")");
+        uint8_t *dst = static_cast<uint8_t *>(host_dst);
+        for (int iz = 0; iz < gr.nz; ++iz) {
+            const int k = iz / P.ns, j = iz % P.ns;
+            const int64_t shift = (int64_t)k * P.geom.views_per_turn + P.n_lo;
+            for (size_t q = 0; q < plane; ++q) {
+                const kats::PiEntry &x = pe[(size_t)j * plane + q];
+                dst[(size_t)iz * plane + q] = (x.nf <= x.nl && x.nf + shift - 1 >= 0 &&
+                                               x.nl + shift + 1 <= P.geom.n_views - 1) ? 1 : 0;
+            }
+        }
+        return KATS_OK;
+    }
     switch (which) {
         case KATS_TABLE_FR_ROW: src = P.fr_row.data(); n = P.fr_row.size() * 4; break;
         case KATS_TABLE_FR_WEIGHT: src = P.fr_w.data(); n = P.fr_w.size() * 8; break;

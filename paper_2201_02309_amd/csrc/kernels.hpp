@@ -39,6 +39,7 @@ struct KParams {
     const float *hil_im;
     const PiEntry *pi;
     const BpBox *boxes;
+    const TileRay *tref;
     int bp_tiles_x, bp_tiles_y, bp_runs, bp_kz;
     int bp_all_fit;                    // every footprint box fits the LDS tile
     int gf_rows, gf_cols;              // padded g^F view (zero border kPad)
@@ -61,26 +62,65 @@ hipError_t launch_rmse_ssim(const float *f, const float *g, unsigned long long n
 // scratch; the address is looked up with hipGetSymbolAddress on a device's first call.
 hipError_t static_scratch(void **out, uint64_t *bytes);
 
-// PI lines (lambda_i, lambda_o) of every voxel of the first n_tab slices, float64, into
-// d_li / d_lo [n_tab][ny][nx].
-hipError_t launch_pi_solve(const katsevich_geometry &g, const katsevich_grid &gr, double h,
-                           int n_tab, double *d_li, double *d_lo, hipStream_t s);
-
 // Forward filter chain on views first_view..last_view:
 //   g2 = deriv+LW(sino); g4 = Hilbert(FR(g2)); gF = cos * BR(g4).
 hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,
                          hipStream_t s);
 // Backprojection of every pitch (reusing the first pitch's tables).
 hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s);
-
 // Grouped backprojection of n bound plans (one launch per group of up to 16 plans, the
 // plans whose boxes fit the LDS tile grouped apart); kz: the plans' common slice run.
 hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, float *const *vol,
                                     int n, int kz, hipStream_t s);
-
 // Adjoint pieces.
 hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFbar, hipStream_t s);
 hipError_t launch_filter_T(const KParams &k, const float *gFbar, float *g4bar, float *g2bar,
                            float *gsino, hipStream_t s);
+
+// ---- Device plan builder (plan_gpu.hip): float64 scalars of the plan, exactly as the host
+// builder holds them.
+struct DevPlanArgs {
+    double R, D, h, lambda0, z0, lambda_first, dlam;
+    double dalpha, col_offset, dw, row_offset;
+    double kscale, psi_max, dpsi, r_fov;
+    double x_first, dx, y_first, dy, z_first, dz;
+    long long n_views;
+    int cols, rows, n_psi, fft_len;
+    int nx, ny, nz, n_tab, ns, Nv;
+    int tiles_x, tiles_y, runs, kz, W_cap;
+};
+
+// Counts the device builder reduces (in scratch; read back once at the end).
+struct DevPlanStats {
+    int nmin, nmax;                  // over voxels in the field of view: first / last covered view
+    int box_rows, box_cols;          // largest footprint box over the tiles' hulls
+    long long vmin, vmax;            // first / last view any valid voxel uses
+    unsigned long long n_vv, n_valid;
+};
+
+struct DevPlanPtrs {
+    // scratch: float64 PI limits (view units) and integer PI tables of the table pitch,
+    // the counts, and float64 copies of the rebinning tables for the host
+    double *li, *lo;
+    int *nf, *nl;
+    unsigned char *fov;
+    DevPlanStats *stats;
+    int *fr_row;
+    double *fr_w, *psi_hat;
+    int *br_k;
+    double *br_w;
+    // the caller's table buffer
+    float4 *view;
+    FrEntry *fr;
+    int *t_br_k;
+    float *t_br_w, *lw, *cos_alpha;
+    float2 *twiddle;
+    float *hil_im;
+    PiEntry *pi;
+    BpBox *boxes;
+    TileRay *tref;
+};
+
+hipError_t launch_plan_device(const DevPlanArgs &a, const DevPlanPtrs &p, hipStream_t s);
 
 }  // namespace kats

@@ -275,15 +275,11 @@ static int table_slices(const katsevich_geometry &g, const katsevich_grid &gr, i
     return std::min(ns, gr.nz);
 }
 
-uint64_t pi_scratch_bytes(const katsevich_geometry &g, const katsevich_grid &gr) {
-    if (!(gr.dz > 0) || gr.nx < 1 || gr.ny < 1 || gr.nz < 1) return 0;
-    const uint64_t nvox = (uint64_t)table_slices(g, gr, nullptr, nullptr) * gr.ny * gr.nx;
-    return 2 * align256(nvox * sizeof(double));
-}
 
-int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
-               const katsevich_options &opts, PlanHost &P, std::string &err,
-               const DevicePiSolve *dev) {
+// Validation, detector coordinates, kappa-line sampling, pitch structure and the Hilbert
+// FFT length: everything both builders share, all of it O(rows + cols + n_psi).
+static int plan_setup(const katsevich_geometry &g_in, const katsevich_grid &gr,
+                      const katsevich_options &opts, PlanHost &P, std::string &err) {
     auto bad = [&](const std::string &m) { err = m; return KATS_EINVAL_GEOMETRY; };
     if (opts.flags & ~KATS_FLAG_HALF_SAMPLE_DERIVATIVE) return bad("unknown option flags");
     // Half-sample derivative: eq. Deriv is taken at the centre of each 2 x 2 cell of the
@@ -366,6 +362,63 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
     P.psi.resize(P.n_psi);
     for (int k = 0; k < P.n_psi; ++k) P.psi[k] = (k - 0.5 * (P.n_psi - 1)) * P.dpsi;
 
+    // ------------------------------------------------------------------ pitches, FFT length
+    P.n_tab = table_slices(g, gr, &P.ns, &P.commensurate);
+    P.n_pitches = (gr.nz + P.ns - 1) / P.ns;
+    P.bp_tiles_x = (gr.nx + kBpTile - 1) / kBpTile;
+    P.bp_tiles_y = (gr.ny + kBpTile - 1) / kBpTile;
+    P.bp_runs = (P.n_tab + P.bp_kz - 1) / P.bp_kz;
+    P.fft_len = 1;
+    while (P.fft_len < 2 * cols - 1) P.fft_len *= 2;
+    P.fft_len = std::max(P.fft_len, 64);          // smallest register-FFT shape
+    P.gf_rows = rows + 2 * kPad;
+    P.gf_cols = (cols + 2 * kPad + 3) & ~3;
+    // |tan(alpha*)| <= tan(alpha_m) for every voxel inside the field of view; other lanes
+    // are discarded (and clamped into their box), so a fit on that range is exact enough
+    fit_atan_columns(std::tan(P.alpha_m) * (1.0 + 1e-4), 1.0 / g.dalpha, P.atan_coef, P.atan_deg);
+    return KATS_OK;
+}
+
+// Byte offsets of the device tables for a pitch window of W views (the host builder knows
+// W exactly, the device builder lays the tables out for an upper bound of it).
+static void make_layout(PlanHost &P, int W) {
+    const katsevich_geometry &g = P.geom;
+    const uint64_t nvox = (uint64_t)P.n_tab * P.grid.ny * P.grid.nx;
+    TableLayout &L = P.layout;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
+    L.view = take((uint64_t)W * 16);
+    L.fr = take((uint64_t)P.n_psi * g.det_cols * sizeof(FrEntry));
+    L.br_k = take((uint64_t)g.det_rows * g.det_cols * 4);
+    L.br_w = take((uint64_t)g.det_rows * g.det_cols * 4);
+    L.lw = take((uint64_t)g.det_rows * 4);
+    L.cos_alpha = take((uint64_t)g.det_cols * 4);
+    L.twiddle = take((uint64_t)P.fft_len * 8);
+    L.hil_im = take((uint64_t)P.fft_len * 4);
+    L.pi = take(nvox * sizeof(PiEntry));
+    L.boxes = take((uint64_t)P.bp_runs * P.bp_tiles_y * P.bp_tiles_x * W * sizeof(BpBox));
+    L.tref = take((uint64_t)P.bp_tiles_y * P.bp_tiles_x * W * sizeof(TileRay));
+    L.total = off;
+}
+
+// Workspace sizes once the filtered view range is known.
+static void set_workspace(PlanHost &P) {
+    const katsevich_geometry &g = P.geom;
+    const int64_t nfilt = std::max<int64_t>(0, P.last_view - P.first_view + 1);
+    P.g4_bytes = align256((uint64_t)nfilt * P.n_psi * g.det_cols * 4);
+    P.g2_bytes = align256((uint64_t)nfilt * g.det_rows * g.det_cols * 4);
+    P.gF_bytes = align256((uint64_t)nfilt * P.gf_rows * P.gf_cols * 4);
+}
+
+int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
+               const katsevich_options &opts, PlanHost &P, std::string &err) {
+    auto bad = [&](const std::string &m) { err = m; return KATS_EINVAL_GEOMETRY; };
+    const int st0 = plan_setup(g_in, gr, opts, P, err);
+    if (st0 != KATS_OK) return st0;
+    const katsevich_geometry &g = P.geom;
+    const int cols = g.det_cols, rows = g.det_rows;
+    const Kappa K{g.D * P.h / g.R};
+
     P.fr_row.resize((size_t)P.n_psi * cols);
     P.fr_w.resize((size_t)P.n_psi * cols);
     for (int k = 0; k < P.n_psi; ++k)
@@ -406,10 +459,6 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
         }
     }
 
-    // ------------------------------------------------------------------ pitches
-    P.n_tab = table_slices(g, gr, &P.ns, &P.commensurate);
-    P.n_pitches = (gr.nz + P.ns - 1) / P.ns;
-
     // ------------------------------------------------------------------ PI limits
     const size_t plane = (size_t)gr.ny * gr.nx;
     const size_t nvox = (size_t)P.n_tab * plane;
@@ -423,25 +472,7 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
         err = "out of host memory for PI tables";
         return KATS_ENOMEM;
     }
-    if (dev) {
-        // lambda_i, lambda_o on the GPU, copied back into pi_li / pi_lo
-        if (dev->bytes < pi_scratch_bytes(g, gr) || !dev->scratch) {
-            err = "PI-line scratch smaller than the plan needs";
-            return KATS_EWORKSPACE;
-        }
-        double *d_li = static_cast<double *>(dev->scratch);
-        double *d_lo = reinterpret_cast<double *>(static_cast<unsigned char *>(dev->scratch) +
-                                                  align256(nvox * sizeof(double)));
-        hipStream_t st = static_cast<hipStream_t>(dev->stream);
-        hipError_t e = launch_pi_solve(g, gr, P.h, P.n_tab, d_li, d_lo, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(P.pi_li.data(), d_li, nvox * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(P.pi_lo.data(), d_lo, nvox * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            err = std::string("GPU PI-line solve: ") + hipGetErrorString(e);
-            return KATS_EHIP;
-        }
-    } else {
+    {
         const PiSolver S{g.R, P.h, g.lambda0, g.z0};
         // per voxel column (x, y), slices in increasing z so each root brackets the next
         const double step = 2.0 * gr.dz / P.h;
@@ -537,9 +568,6 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
     // ------------------------------------------------------------------ Hilbert spectrum
     // taps K[m] = 2 dalpha / (pi sin(m dalpha)) for odd m, 0 for even m; real and odd, so the
     // length-N DFT of the wrapped taps is i * Im with Im[f] = -2 sum_{m odd} K[m] sin(2 pi f m/N).
-    P.fft_len = 1;
-    while (P.fft_len < 2 * cols - 1) P.fft_len *= 2;
-    P.fft_len = std::max(P.fft_len, 64);          // smallest register-FFT shape
     const int N = P.fft_len;
     P.hil_im.assign(N, 0.0);
     for (int f = 0; f < N; ++f) {
@@ -553,24 +581,8 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
     }
 
     // ------------------------------------------------------------------ device image
-    TableLayout &L = P.layout;
-    uint64_t off = 0;
-    auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
-    L.view = take((uint64_t)P.W * 16);
-    L.fr = take((uint64_t)P.n_psi * cols * sizeof(FrEntry));
-    L.br_k = take((uint64_t)rows * cols * 4);
-    L.br_w = take((uint64_t)rows * cols * 4);
-    L.lw = take((uint64_t)rows * 4);
-    L.cos_alpha = take((uint64_t)cols * 4);
-    L.twiddle = take((uint64_t)N * 8);
-    L.hil_im = take((uint64_t)N * 4);
-    L.pi = take((uint64_t)nvox * sizeof(PiEntry));
-    P.bp_tiles_x = (gr.nx + kBpTile - 1) / kBpTile;
-    P.bp_tiles_y = (gr.ny + kBpTile - 1) / kBpTile;
-    P.bp_runs = (P.n_tab + P.bp_kz - 1) / P.bp_kz;
-    const uint64_t n_boxes = (uint64_t)P.bp_runs * P.bp_tiles_y * P.bp_tiles_x * P.W;
-    L.boxes = take(n_boxes * sizeof(BpBox));
-    L.total = off;
+    make_layout(P, P.W);
+    const TableLayout &L = P.layout;
     try {
         P.image.assign(L.total, 0);
     } catch (...) {
@@ -639,6 +651,7 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
     // in the kernel; the box is clipped to the zero-padded detector.
     {
         BpBox *bx = reinterpret_cast<BpBox *>(img + L.boxes);
+        TileRay *tr = reinterpret_cast<TileRay *>(img + L.tref);
         const double col_c = 0.5 * (cols - 1) - g.col_offset;
         const double row_c = 0.5 * (rows - 1) - g.row_offset;
         const int tiles = P.bp_tiles_y * P.bp_tiles_x;
@@ -650,6 +663,8 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
             const double y0 = gr.y_first + (double)ty * kBpTile * gr.dy;
             const double y1 = gr.y_first + (double)(ty * kBpTile + kBpTile - 1) * gr.dy;
             const double cx[4] = {x0, x1, x0, x1}, cy[4] = {y0, y0, y1, y1};
+            const double xc = gr.x_first + (tx * kBpTile + 0.5 * (kBpTile - 1)) * gr.dx;
+            const double yc = gr.y_first + (ty * kBpTile + 0.5 * (kBpTile - 1)) * gr.dy;
             auto clip = [](double lo, double hi, int n) {
                 // cells [lo, hi] clipped to [-kPad, n-1+kPad], at least two cells
                 double a = std::floor(lo) - 1.0, c = std::floor(hi) + 2.0;
@@ -684,6 +699,12 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
                 const int shift = (cc.first + kPad) & 3;
                 cc.first -= shift;
                 cc.second += shift;
+                {
+                    const double uc = -xc * sb + yc * cb, vc = g.R - xc * cb - yc * sb;
+                    const double col = std::atan2(uc, vc) / g.dalpha + col_c - cc.first;
+                    tr[(size_t)t * P.W + m] = TileRay{(float)col, (float)uc, (float)vc,
+                                                      (float)(uc * uc + vc * vc)};
+                }
                 const double e = gr.z_first - g.z0 - P.h * lam;
                 for (int run = 0; run < P.bp_runs; ++run) {
                     const double dz0 = e + (double)(run * P.bp_kz) * gr.dz;
@@ -739,17 +760,215 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
     }
 
     // ------------------------------------------------------------------ workspace sizes
-    const int64_t nfilt = std::max<int64_t>(0, P.last_view - P.first_view + 1);
-    P.g4_bytes = align256((uint64_t)nfilt * P.n_psi * cols * 4);
-    P.g2_bytes = align256((uint64_t)nfilt * rows * cols * 4);
-    P.gf_rows = rows + 2 * kPad;
-    P.gf_cols = (cols + 2 * kPad + 3) & ~3;
-    P.gF_bytes = align256((uint64_t)nfilt * P.gf_rows * P.gf_cols * 4);
+    set_workspace(P);
+    return KATS_OK;
+}
 
-    // ------------------------------------------------------------------ atan polynomial
-    // |tan(alpha*)| <= tan(alpha_m) for every voxel inside the field of view; other lanes
-    // are discarded (and clamped into their box), so a fit on that range is exact enough
-    fit_atan_columns(std::tan(P.alpha_m) * (1.0 + 1e-4), 1.0 / g.dalpha, P.atan_coef, P.atan_deg);
+// ---------------------------------------------------------------------------------
+// Device builder (kernels in plan_gpu.hip)
+// ---------------------------------------------------------------------------------
+
+// Byte offsets inside the device builder's scratch buffer.
+struct ScratchLayout {
+    uint64_t li, lo, nf, nl, fov, stats, fr_row, fr_w, psi_hat, br_k, br_w, total;
+};
+
+static ScratchLayout scratch_layout(const PlanHost &P) {
+    const uint64_t nvox = (uint64_t)P.n_tab * P.grid.ny * P.grid.nx;
+    const uint64_t rc = (uint64_t)P.geom.det_rows * P.geom.det_cols;
+    const uint64_t pc = (uint64_t)P.n_psi * P.geom.det_cols;
+    ScratchLayout S{};
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
+    S.li = take(nvox * 8);
+    S.lo = take(nvox * 8);
+    S.nf = take(nvox * 4);
+    S.nl = take(nvox * 4);
+    S.fov = take(nvox);
+    S.stats = take(sizeof(DevPlanStats));
+    S.fr_row = take(pc * 4);
+    S.fr_w = take(pc * 8);
+    S.psi_hat = take(rc * 8);
+    S.br_k = take(rc * 4);
+    S.br_w = take(rc * 8);
+    S.total = off;
+    return S;
+}
+
+// Upper bound of the pitch window W over the voxels in the field of view (r <= r_fov):
+// on the PI line of a point at height z, lambda_i = z_r - g (1 + tau) and lambda_o =
+// z_r + g (1 - tau) with z_r = (z - z0)/h, half-span g <= pi/2 + asin(r_fov/R) and
+// |tau| <= r_fov/R, so the covered views of the table slices lie within
+// [z_r(first) - G, z_r(last) + G], G = (pi/2 + asin(s))(1 + s), s = r_fov/R, plus the
+// rounding of the first / last covered view and the two margin views.
+static int window_cap(const PlanHost &P) {
+    const katsevich_geometry &g = P.geom;
+    const katsevich_grid &gr = P.grid;
+    const double zr0 = (gr.z_first - g.z0) / P.h;
+    const double zr1 = (gr.z_first + (P.n_tab - 1) * gr.dz - g.z0) / P.h;
+    const double s = std::min(P.r_fov / g.R, 1.0);
+    const double G = (0.5 * kPi + std::asin(s)) * (1.0 + s);
+    const double span = (zr1 - zr0) + 2.0 * G;
+    return (int)std::ceil(span / P.dlam) + 8;
+}
+
+int device_plan_sizes(const katsevich_geometry &g, const katsevich_grid &gr,
+                      const katsevich_options &opts, uint64_t &scratch_bytes,
+                      uint64_t &table_bytes, std::string &err) {
+    PlanHost P;
+    const int st = plan_setup(g, gr, opts, P, err);
+    if (st != KATS_OK) return st;
+    make_layout(P, window_cap(P));
+    scratch_bytes = scratch_layout(P).total;
+    table_bytes = P.layout.total;
+    return KATS_OK;
+}
+
+int device_plan_scratch_offsets(const katsevich_geometry &g, const katsevich_grid &gr,
+                                const katsevich_options &opts, uint64_t off[5], int &n_tab,
+                                std::string &err) {
+    PlanHost P;
+    const int st = plan_setup(g, gr, opts, P, err);
+    if (st != KATS_OK) return st;
+    const ScratchLayout S = scratch_layout(P);
+    off[0] = S.li;
+    off[1] = S.lo;
+    off[2] = S.nf;
+    off[3] = S.nl;
+    off[4] = S.fov;
+    n_tab = P.n_tab;
+    return KATS_OK;
+}
+
+int build_plan_device(const katsevich_geometry &g_in, const katsevich_grid &gr,
+                      const katsevich_options &opts, PlanHost &P, std::string &err,
+                      const DevicePlanBuffers &buf) {
+    const int st0 = plan_setup(g_in, gr, opts, P, err);
+    if (st0 != KATS_OK) return st0;
+    const katsevich_geometry &g = P.geom;
+    const int W_cap = window_cap(P);
+    make_layout(P, W_cap);
+    const ScratchLayout S = scratch_layout(P);
+    if (!buf.scratch || buf.scratch_bytes < S.total) {
+        err = "scratch smaller than katsevich_plan_device_sizes says";
+        return KATS_EWORKSPACE;
+    }
+    if (!buf.tables || buf.table_bytes < P.layout.total) {
+        err = "table buffer smaller than katsevich_plan_device_sizes says";
+        return KATS_ESHAPE;
+    }
+    DevPlanArgs a{};
+    a.R = g.R;
+    a.D = g.D;
+    a.h = P.h;
+    a.lambda0 = g.lambda0;
+    a.z0 = g.z0;
+    a.lambda_first = g.lambda_first;
+    a.dlam = P.dlam;
+    a.dalpha = g.dalpha;
+    a.col_offset = g.col_offset;
+    a.dw = g.dw;
+    a.row_offset = g.row_offset;
+    a.kscale = g.D * P.h / g.R;
+    a.psi_max = P.psi_max;
+    a.dpsi = P.dpsi;
+    a.r_fov = P.r_fov;
+    a.x_first = gr.x_first;
+    a.dx = gr.dx;
+    a.y_first = gr.y_first;
+    a.dy = gr.dy;
+    a.z_first = gr.z_first;
+    a.dz = gr.dz;
+    a.n_views = g.n_views;
+    a.cols = g.det_cols;
+    a.rows = g.det_rows;
+    a.n_psi = P.n_psi;
+    a.fft_len = P.fft_len;
+    a.nx = gr.nx;
+    a.ny = gr.ny;
+    a.nz = gr.nz;
+    a.n_tab = P.n_tab;
+    a.ns = P.ns;
+    a.Nv = g.views_per_turn;
+    a.tiles_x = P.bp_tiles_x;
+    a.tiles_y = P.bp_tiles_y;
+    a.runs = P.bp_runs;
+    a.kz = P.bp_kz;
+    a.W_cap = W_cap;
+    unsigned char *sc = static_cast<unsigned char *>(buf.scratch);
+    unsigned char *tb = static_cast<unsigned char *>(buf.tables);
+    const TableLayout &L = P.layout;
+    DevPlanPtrs p{};
+    p.li = reinterpret_cast<double *>(sc + S.li);
+    p.lo = reinterpret_cast<double *>(sc + S.lo);
+    p.nf = reinterpret_cast<int *>(sc + S.nf);
+    p.nl = reinterpret_cast<int *>(sc + S.nl);
+    p.fov = sc + S.fov;
+    p.stats = reinterpret_cast<DevPlanStats *>(sc + S.stats);
+    p.fr_row = reinterpret_cast<int *>(sc + S.fr_row);
+    p.fr_w = reinterpret_cast<double *>(sc + S.fr_w);
+    p.psi_hat = reinterpret_cast<double *>(sc + S.psi_hat);
+    p.br_k = reinterpret_cast<int *>(sc + S.br_k);
+    p.br_w = reinterpret_cast<double *>(sc + S.br_w);
+    p.view = reinterpret_cast<float4 *>(tb + L.view);
+    p.fr = reinterpret_cast<FrEntry *>(tb + L.fr);
+    p.t_br_k = reinterpret_cast<int *>(tb + L.br_k);
+    p.t_br_w = reinterpret_cast<float *>(tb + L.br_w);
+    p.lw = reinterpret_cast<float *>(tb + L.lw);
+    p.cos_alpha = reinterpret_cast<float *>(tb + L.cos_alpha);
+    p.twiddle = reinterpret_cast<float2 *>(tb + L.twiddle);
+    p.hil_im = reinterpret_cast<float *>(tb + L.hil_im);
+    p.pi = reinterpret_cast<PiEntry *>(tb + L.pi);
+    p.boxes = reinterpret_cast<BpBox *>(tb + L.boxes);
+    p.tref = reinterpret_cast<TileRay *>(tb + L.tref);
+
+    const size_t pc = (size_t)P.n_psi * g.det_cols, rc = (size_t)g.det_rows * g.det_cols;
+    P.fr_row.resize(pc);
+    P.fr_w.resize(pc);
+    P.psi_hat.resize(rc);
+    P.br_k.resize(rc);
+    P.br_w.resize(rc);
+    DevPlanStats stats{};
+    hipStream_t s = static_cast<hipStream_t>(buf.stream);
+    hipError_t e = launch_plan_device(a, p, s);
+    // the counts and the float64 rebinning tables (kept on the host for export) come back
+    if (e == hipSuccess) e = hipMemcpyAsync(&stats, p.stats, sizeof(stats), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.fr_row.data(), p.fr_row, pc * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.fr_w.data(), p.fr_w, pc * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.psi_hat.data(), p.psi_hat, rc * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.br_k.data(), p.br_k, rc * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.br_w.data(), p.br_w, rc * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        err = std::string("device plan: ") + hipGetErrorString(e);
+        return KATS_EHIP;
+    }
+    if (stats.nmin > stats.nmax) {
+        err = "no voxel of the grid lies inside the field of view";
+        return KATS_EINVAL_GEOMETRY;
+    }
+    P.n_lo = stats.nmin - 1;
+    P.n_hi = stats.nmax + 1;
+    P.W = P.n_hi - P.n_lo + 1;
+    if (P.W > W_cap) {   // excluded by window_cap's bound; refuse rather than overrun the tables
+        err = "pitch window " + std::to_string(P.W) + " exceeds its bound " + std::to_string(W_cap);
+        return KATS_EINVAL_GEOMETRY;
+    }
+    P.n_vv = (int64_t)stats.n_vv;
+    P.n_valid = (int64_t)stats.n_valid;
+    if (P.n_valid == 0) {
+        P.first_view = 1;
+        P.last_view = 0;   // empty
+    } else {
+        P.first_view = stats.vmin;
+        P.last_view = stats.vmax;
+    }
+    P.bp_box_rows = stats.box_rows;
+    P.bp_box_cols = stats.box_cols;
+    set_workspace(P);
+    P.d_tables = buf.tables;
+    P.device_built = true;
+    P.W_cap = W_cap;
     return KATS_OK;
 }
 

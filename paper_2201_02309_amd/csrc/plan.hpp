@@ -47,6 +47,16 @@ struct BpBox {
 };
 static_assert(sizeof(BpBox) == 8, "BpBox must be 8 bytes");
 
+// The ray from the source to the centre (x_c, y_c) of a backprojection tile at one window
+// view, from float64: u_c = -x_c sin(beta) + y_c cos(beta), v_c = R - x_c cos(beta) - y_c
+// sin(beta), col = its column coordinate atan2(u_c, v_c)/dalpha + col_c relative to the
+// tile's footprint box column c0.  The adjoint backprojector measures a voxel's column from
+// it (small in-tile offsets in float32) instead of from the detector centre.
+struct TileRay {
+    float col, uc, vc, rho2;   // rho2 = u_c^2 + v_c^2
+};
+static_assert(sizeof(TileRay) == 16, "TileRay must be 16 bytes");
+
 // Forward height rebinning of one (kappa-line, column): rows r0, r0+1 with weight w on r0+1.
 struct FrEntry {
     int32_t r0;
@@ -66,6 +76,7 @@ struct TableLayout {
     uint64_t hil_im = 0;     // float  [fft_len]  Im(DFT of the Hilbert taps) / N
     uint64_t pi = 0;         // PiEntry [n_tab][ny][nx]
     uint64_t boxes = 0;      // BpBox   [runs][tiles_y][tiles_x][W]
+    uint64_t tref = 0;       // float4  [tiles_y][tiles_x][W]  the tile centre's ray (see below)
     uint64_t total = 0;
 };
 
@@ -108,6 +119,10 @@ struct PlanHost {
     TableLayout layout;
     std::vector<unsigned char> image;      // table_bytes, copied by katsevich_plan_bind
     void *d_tables = nullptr;              // caller memory after bind
+    // device-built plan: the tables were computed in place in d_tables (no host image, no
+    // host PI tables); W_cap is the window bound its view and box tables are laid out for
+    bool device_built = false;
+    int W_cap = 0;
 
     // padded g^F view: [gf_rows][gf_cols], gf_cols a multiple of 4 (16-byte rows)
     int gf_rows = 0, gf_cols = 0;
@@ -121,22 +136,36 @@ struct PlanHost {
     uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0;   // gF: padded [n][rows+2kPad][cols+2kPad]
 };
 
-// Device resources for solving the PI lines on the GPU (scratch of pi_scratch_bytes()).
-struct DevicePiSolve {
+// Build the plan on the host in float64; returns a KATS_* status and fills err on failure.
+int build_plan(const katsevich_geometry &g, const katsevich_grid &grid,
+               const katsevich_options &opts, PlanHost &P, std::string &err);
+
+// Caller buffers of the device plan builder (sizes from device_plan_sizes).
+struct DevicePlanBuffers {
     void *scratch;
-    uint64_t bytes;
+    uint64_t scratch_bytes;
+    void *tables;
+    uint64_t table_bytes;
     void *stream;
 };
 
-// Build the plan; returns a KATS_* status and fills err on failure.  With dev, the PI lines
-// of one pitch are solved on the GPU (float64, same iteration) and the rest on the host.
-int build_plan(const katsevich_geometry &g, const katsevich_grid &grid,
-               const katsevich_options &opts, PlanHost &P, std::string &err,
-               const DevicePiSolve *dev = nullptr);
+// Scratch and table bytes the device builder needs for this geometry, grid and options.
+int device_plan_sizes(const katsevich_geometry &g, const katsevich_grid &grid,
+                      const katsevich_options &opts, uint64_t &scratch_bytes,
+                      uint64_t &table_bytes, std::string &err);
 
-// Device scratch the GPU PI solve needs for this geometry and grid (two float64 per voxel
-// of one pitch's slices).
-uint64_t pi_scratch_bytes(const katsevich_geometry &g, const katsevich_grid &grid);
+// Offsets in the device builder's scratch of its float64 PI limits (view units) li, lo,
+// int32 first / last covered views nf, nl and uint8 field-of-view flags, each
+// [n_tab][ny][nx]; they hold the table pitch's values when build_plan_device returns.
+int device_plan_scratch_offsets(const katsevich_geometry &g, const katsevich_grid &grid,
+                                const katsevich_options &opts, uint64_t off[5], int &n_tab,
+                                std::string &err);
+
+// Build the plan on the GPU in float64, straight into buf.tables (the plan is bound to it);
+// one synchronisation of buf.stream at the end.
+int build_plan_device(const katsevich_geometry &g, const katsevich_grid &grid,
+                      const katsevich_options &opts, PlanHost &P, std::string &err,
+                      const DevicePlanBuffers &buf);
 
 // Validity of voxel (iz, iy, ix) (integer decision taken from the float64 tables).
 bool voxel_valid(const PlanHost &P, int iz, int iy, int ix);

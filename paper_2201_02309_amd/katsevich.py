@@ -42,6 +42,13 @@ class _Options(ctypes.Structure):
                 ("bp_slices", c_int32)]
 
 
+class _DevSizes(ctypes.Structure):
+    _fields_ = [("scratch_bytes", c_uint64), ("table_bytes", c_uint64),
+                ("pi_li_offset", c_uint64), ("pi_lo_offset", c_uint64),
+                ("pi_nfirst_offset", c_uint64), ("pi_nlast_offset", c_uint64),
+                ("fov_offset", c_uint64), ("n_table_slices", c_int32), ("reserved", c_int32)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("table_bytes", c_uint64), ("workspace_bytes", c_uint64),
                 ("filtered_bytes", c_uint64), ("workspace_bytes_filter", c_uint64),
@@ -69,7 +76,7 @@ EXPORTED = ["katsevich_plan", "katsevich_plan_query", "katsevich_plan_bind",
             "katsevich_plan_export", "katsevich_recon", "katsevich_filter",
             "katsevich_backproject", "katsevich_recon_backward", "katsevich_backproject_batch",
             "katsevich_plan_destroy", "katsevich_status_string", "katsevich_last_error",
-            "katsevich_plan_device", "katsevich_plan_device_scratch_bytes",
+            "katsevich_plan_device", "katsevich_plan_device_sizes",
             "katsevich_sparse_upsample", "katsevich_data_scratch_bytes", "katsevich_max",
             "katsevich_add_noise", "katsevich_rmse_ssim", "katsevich_rmse_ssim_noscratch"]
 
@@ -98,10 +105,12 @@ def load_library(path: str = LIB_PATH):
     lib.katsevich_backproject_batch.argtypes = [POINTER(c_void_p), POINTER(c_void_p),
                                                 POINTER(c_void_p), c_int, c_void_p]
     lib.katsevich_plan_device.argtypes = [POINTER(_Geometry), POINTER(_Grid), POINTER(_Options),
-                                          c_void_p, c_uint64, c_void_p, POINTER(c_void_p)]
+                                          c_void_p, c_uint64, c_void_p, c_uint64, c_void_p,
+                                          POINTER(c_void_p)]
     lib.katsevich_plan_device.restype = c_int
-    lib.katsevich_plan_device_scratch_bytes.argtypes = [POINTER(_Geometry), POINTER(_Grid)]
-    lib.katsevich_plan_device_scratch_bytes.restype = c_uint64
+    lib.katsevich_plan_device_sizes.argtypes = [POINTER(_Geometry), POINTER(_Grid), POINTER(_Options),
+                                                POINTER(_DevSizes)]
+    lib.katsevich_plan_device_sizes.restype = c_int
     lib.katsevich_sparse_upsample.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p]
     lib.katsevich_sparse_upsample.restype = c_int
     lib.katsevich_data_scratch_bytes.argtypes = []
@@ -163,15 +172,21 @@ class Plan:
 
     def __init__(self, geom: dict, grid: dict, n_psi: int = 0, n_threads: int = 0,
                  bind: bool = True, device=None, bp_slices: int = 0, gpu_plan: bool = False,
-                 half_sample: bool = False):
-        """gpu_plan: solve the PI lines on the GPU (katsevich_plan_device) with a scratch
-        tensor on `device` and its current stream; otherwise everything on the host.
+                 half_sample: bool = False, keep_pi_scratch: bool = False):
+        """gpu_plan: build the whole plan on the GPU (katsevich_plan_device) on `device` and
+        its current stream, straight into the plan's table tensor (the plan is then bound
+        whatever `bind` says); otherwise on the host (katsevich_plan).  keep_pi_scratch
+        (gpu_plan only): keep the build's scratch, whose float64 PI tables pi_tables() reads.
         half_sample: KATS_FLAG_HALF_SAMPLE_DERIVATIVE (derivative at the centres of the
         sinogram's 2 x 2 (lambda, alpha) cells)."""
         self._lib = load_library()
         self.geom = dict(geom)
         self.grid = dict(grid)
         self._h = c_void_p()
+        self.tables = None
+        self._ws = None
+        self.device = None
+        self._pi_scratch = None
         opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads),
                         flags=FLAG_HALF_SAMPLE_DERIVATIVE if half_sample else 0,
                         bp_slices=int(bp_slices))
@@ -179,11 +194,19 @@ class Plan:
         if gpu_plan:
             import torch
             dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-            need = int(self._lib.katsevich_plan_device_scratch_bytes(byref(g), byref(gr)))
-            scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
-            _check(self._lib, self._lib.katsevich_plan_device(
-                byref(g), byref(gr), byref(opts), c_void_p(scratch.data_ptr()),
-                c_uint64(scratch.numel()), _stream_handle(dev), byref(self._h)))
+            sz = _DevSizes()
+            _check(self._lib, self._lib.katsevich_plan_device_sizes(byref(g), byref(gr), byref(opts),
+                                                                    byref(sz)))
+            with torch.cuda.device(dev):
+                scratch = torch.empty(max(int(sz.scratch_bytes), 256), dtype=torch.uint8, device=dev)
+                tables = torch.empty(max(int(sz.table_bytes), 256), dtype=torch.uint8, device=dev)
+                _check(self._lib, self._lib.katsevich_plan_device(
+                    byref(g), byref(gr), byref(opts), c_void_p(scratch.data_ptr()),
+                    c_uint64(scratch.numel()), c_void_p(tables.data_ptr()), c_uint64(tables.numel()),
+                    _stream_handle(dev), byref(self._h)))
+            self.tables, self.device = tables, dev
+            if keep_pi_scratch:
+                self._pi_scratch = (scratch, {k: getattr(sz, k) for k, _ in _DevSizes._fields_})
             del scratch
         else:
             _check(self._lib, self._lib.katsevich_plan(byref(g), byref(gr), byref(opts),
@@ -191,11 +214,26 @@ class Plan:
         info = _Info()
         _check(self._lib, self._lib.katsevich_plan_query(self._h, byref(info)))
         self.info = {k: getattr(info, k) for k, _ in _Info._fields_}
-        self.tables = None
-        self._ws = None
-        self.device = None
-        if bind:
+        if bind and self.tables is None:
             self.bind(device)
+
+    def pi_tables(self) -> dict:
+        """Float64 PI tables of a plan built with gpu_plan=True, keep_pi_scratch=True, read
+        from the build's scratch: li, lo (view units), nf, nl (first / last covered view),
+        fov, each [n_table_slices, ny, nx]."""
+        if self._pi_scratch is None:
+            raise KatsevichError(-1, "pi_tables needs a plan built with gpu_plan=True, keep_pi_scratch=True")
+        scratch, sz = self._pi_scratch
+        n = int(sz["n_table_slices"]) * int(self.grid["ny"]) * int(self.grid["nx"])
+        shape = (int(sz["n_table_slices"]), int(self.grid["ny"]), int(self.grid["nx"]))
+        host = scratch.cpu().numpy()
+        out = {}
+        for key, off, dt in (("li", "pi_li_offset", np.float64), ("lo", "pi_lo_offset", np.float64),
+                             ("nf", "pi_nfirst_offset", np.int32), ("nl", "pi_nlast_offset", np.int32),
+                             ("fov", "fov_offset", np.uint8)):
+            o = int(sz[off])
+            out[key] = host[o:o + n * np.dtype(dt).itemsize].view(dt).reshape(shape).copy()
+        return out
 
     # ------------------------------------------------------------------ device side
     def bind(self, device=None):

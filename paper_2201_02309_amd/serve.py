@@ -3,9 +3,9 @@
 Requests (a scan geometry, a voxel grid and a device-resident sinogram) arrive over time.
 The server
 
-* builds the float64 plan of each new geometry on worker threads (the PI lines on the GPU,
-  the rest on the host; plans are cached by the exact geometry/grid tuple and bound to
-  device tables once),
+* builds the float64 plan of each new geometry on worker threads (on the GPU, straight into
+  device tables; plans are cached by the exact geometry/grid tuple, least recently used
+  ones dropped beyond a table budget once no request in flight holds them),
 * admits ready requests first-come-first-served while their device footprint (sinogram
   copy, filter workspace, g^F, volume) gets a contiguous block of the server's HBM arena
   (one buffer of the budget's size, first-fit), otherwise they wait until earlier requests
@@ -57,6 +57,8 @@ class Request:
     cache_hit: bool = False
     plan_seconds: float = 0.0
     footprint: int = 0
+    valid_voxels: int = 0        # voxels the plan reconstructs (the rest of the grid is 0)
+    plan_key: object = None
     offset: int = 0              # arena byte offset while in flight
     volume: object = None
     error: str = ""              # non-empty: rejected (plan failed or footprint too large)
@@ -71,22 +73,55 @@ class PlanFailed(RuntimeError):
 
 
 class PlanCache:
-    """Plans keyed by geometry; built and bound on worker threads (each worker binds on its
-    own stream, so the serving streams never wait for a table upload)."""
+    """Plans keyed by geometry; built on worker threads, each on its own stream (on the GPU
+    by default: katsevich_plan_device writes the tables straight into device memory, so the
+    serving streams never wait for a table upload).  Cached plans are kept while their tables
+    fit table_budget bytes; beyond it the least recently used plans that no request in
+    flight holds (acquire / release) are dropped."""
 
-    def __init__(self, device, workers=2, n_psi=0, bp_slices=0, gpu_plan=True):
+    def __init__(self, device, workers=2, n_psi=0, bp_slices=0, gpu_plan=True,
+                 table_budget: float = 32e9):
         self.device = device
         self.n_psi, self.bp_slices = n_psi, bp_slices
-        self.gpu_plan = gpu_plan                   # PI lines on the GPU (katsevich_plan_device)
-        self.plans = {}
+        self.gpu_plan = gpu_plan                   # plans built on the GPU (katsevich_plan_device)
+        self.table_budget = float(table_budget)
+        self.plans = collections.OrderedDict()     # least recently used first
         self.pending = {}
         self.failed = {}
         self.build_seconds = {}
-        self.hits = self.misses = 0
+        self.inuse = collections.Counter()
+        self.hits = self.misses = self.evicted = 0
         self.table_bytes = 0
         self._lock = threading.Lock()
         self._pool = ThreadPoolExecutor(max_workers=workers)
         self._streams = {}
+
+    def acquire(self, key):
+        """A request in flight holds the plan of key (it is not evicted meanwhile)."""
+        with self._lock:
+            self.inuse[key] += 1
+            if key in self.plans:
+                self.plans.move_to_end(key)
+
+    def release(self, key):
+        with self._lock:
+            self.inuse[key] -= 1
+            if self.inuse[key] <= 0:
+                del self.inuse[key]
+            self._evict()
+
+    def _evict(self):
+        # caller holds the lock
+        if self.table_bytes <= self.table_budget:
+            return
+        for key in list(self.plans):
+            if self.table_bytes <= self.table_budget:
+                break
+            if self.inuse.get(key, 0) > 0:
+                continue
+            plan = self.plans.pop(key)
+            self.table_bytes -= int(plan.info["table_bytes"])
+            self.evicted += 1
 
     def _build(self, geom, grid):
         import torch
@@ -98,9 +133,11 @@ class PlanCache:
                 s = self._streams[tid] = torch.cuda.Stream(device=self.device)
         index = self.device.index if hasattr(self.device, "index") else self.device
         with torch.cuda.stream(s):
+            # a device-built plan is bound to the table buffer it was built in
             plan = K.Plan(geom, grid, n_psi=self.n_psi, bind=False, bp_slices=self.bp_slices,
                           gpu_plan=self.gpu_plan, device=index)
-            plan.bind(index)
+            if plan.tables is None:
+                plan.bind(index)
         return plan, time.perf_counter() - t0
 
     def request(self, geom, grid):
@@ -109,6 +146,7 @@ class PlanCache:
         with self._lock:
             if key in self.plans:
                 self.hits += 1
+                self.plans.move_to_end(key)
                 return key, True
             self.misses += 1
             if key not in self.pending:
@@ -139,7 +177,8 @@ class PlanCache:
                 self.build_seconds[key] = secs
                 self.table_bytes += int(plan.info["table_bytes"])
                 self.pending.pop(key, None)
-            return self.plans[key]
+                self._evict()
+            return plan
 
     def get_blocking(self, geom, grid):
         """Plan of (geom, grid), waiting for its build (raises PlanFailed)."""
@@ -284,11 +323,11 @@ class Server:
             ev.record(s)
         return ev, vols
 
-    @staticmethod
-    def _reject(r, why, t0, done):
+    def _reject(self, r, why, t0, done):
         """Complete request r with an error; the loop goes on with the others."""
         r.error = why
         r.t_done = time.perf_counter() - t0
+        self.cache.release(r.plan_key)
         done.append(r)
 
     def run(self, requests, clock_start=None):
@@ -307,7 +346,9 @@ class Server:
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
                 key, hit = self.cache.request(r.geom, r.grid)
+                self.cache.acquire(key)                # held until the request completes
                 r.cache_hit = hit
+                r.plan_key = key
                 waiting.append((r, key))
             # completions: the group's stream has finished, its arena blocks are free again
             for si, item in enumerate(inflight):
@@ -320,6 +361,7 @@ class Server:
                             r.volume = v.clone()
                             torch.cuda.current_stream(self.device).synchronize()
                         self.arena.release(r.offset, r.footprint)
+                        self.cache.release(r.plan_key)
                         done.append(r)
                     inflight[si] = None
             # admission into a free stream (first come, first served)
@@ -342,6 +384,7 @@ class Server:
                         r.t_plan_ready = time.perf_counter() - t0
                         r.plan_seconds = self.cache.build_seconds.get(key, 0.0)
                         r.footprint = footprint(plan)
+                        r.valid_voxels = int(plan.info["n_valid_voxels"])
                         if r.footprint > self.arena.size:
                             self._reject(r, f"footprint {r.footprint} B exceeds the budget "
                                             f"{self.arena.size} B", t0, done)
@@ -379,15 +422,19 @@ def serve_sequential(plan_cache: PlanCache, requests, keep_volumes=False):
         while time.perf_counter() - t0 < r.arrival:
             time.sleep(0.0002)
         key, hit = plan_cache.request(r.geom, r.grid)
+        plan_cache.acquire(key)
         r.cache_hit = hit
+        r.plan_key = key
         try:
             plan = plan_cache.get_blocking(r.geom, r.grid)
         except PlanFailed as exc:
             r.error = str(exc)
             r.t_done = time.perf_counter() - t0
+            plan_cache.release(key)
             continue
         r.t_plan_ready = r.t_admit = time.perf_counter() - t0
         r.plan_seconds = plan_cache.build_seconds.get(key, 0.0)
+        r.valid_voxels = int(plan.info["n_valid_voxels"])
         if r.ready is not None:
             torch.cuda.current_stream(r.sino.device).wait_event(r.ready)
         sino = r.sino.clone()
@@ -397,6 +444,7 @@ def serve_sequential(plan_cache: PlanCache, requests, keep_volumes=False):
         r.volume = vol if keep_volumes else None
         del sino
         plan.release_workspace()
+        plan_cache.release(key)
     return reqs
 
 
@@ -406,8 +454,15 @@ def summarize(reqs):
     lat = np.array([r.latency for r in reqs])
     first = min(r.arrival for r in reqs)
     last = max(r.t_done for r in reqs)
+    plan_s = np.array([r.plan_seconds for r in reqs if not r.cache_hit] or [0.0])
     return {"requests": len(reqs), "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_latency_ms": float(lat.mean() * 1e3), "makespan_s": float(last - first),
             "volumes_per_s": float(len(reqs) / max(last - first, 1e-9)),
-            "cache_hits": int(sum(r.cache_hit for r in reqs)), "rejected": len(rejected)}
+            "cache_hits": int(sum(r.cache_hit for r in reqs)),
+            "cache_hit_rate": float(np.mean([r.cache_hit for r in reqs])),
+            "plan_build_ms_mean": float(plan_s.mean() * 1e3),
+            "plan_build_ms_max": float(plan_s.max() * 1e3), "rejected": len(rejected),
+            "valid_voxel_fraction": float(sum(r.valid_voxels for r in reqs) /
+                                          max(1, sum(int(r.grid["nx"]) * int(r.grid["ny"]) *
+                                                     int(r.grid["nz"]) for r in reqs)))}

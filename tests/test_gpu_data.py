@@ -66,7 +66,14 @@ def test_noise_parity_and_determinism(case):
     noise_ref = ref - sino
     rel = np.linalg.norm((got - sino) - noise_ref) / np.linalg.norm(noise_ref)
     mx = np.abs(got - ref).max()
-    print(f"[parity] noise: noise-part rel-L2 {rel:.3e}, max-abs {mx:.3e} (M {M:.2f})", flush=True)
+    rel_out = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"[parity] noise: noisy sinogram rel-L2 {rel_out:.3e}; noise-part rel-L2 {rel:.3e}, "
+          f"max-abs {mx:.3e} (M {M:.2f})", flush=True)
+    # The noisy sinogram itself meets the 1e-5 bar by orders of magnitude.  Its noise part
+    # (about 0.5 % of M here) is a difference of two float32 numbers of size ~M: storing the
+    # float32 output alone moves it by up to half an ulp of M (~2e-6 at M = 62), i.e. ~1e-5
+    # of the noise part, before any arithmetic, so that part is held to 1e-4.
+    assert rel_out <= 1e-5
     assert rel <= 1e-4 and mx <= 2e-5 * M
 
 
@@ -105,10 +112,12 @@ def test_sparse_noisy_chain_parity(case):
     fi_ref, valid = O.recon(scan, gr, in_ref.astype(np.float32), tables=tab, ftables=ftab)
     fg_ref, _ = O.recon(scan, gr, sino, tables=tab, ftables=ftab)
     r_rmse, r_ssim = D.rmse(fi_ref, fg_ref), D.ssim(fi_ref, fg_ref)
-    print(f"[parity] chain: GPU rmse {m[0]:.6g} ssim {m[1]:.6g} | oracle rmse {r_rmse:.6g} "
-          f"ssim {r_ssim:.6g}", flush=True)
+    print(f"[parity] chain: GPU rmse {m[0]:.10g} ssim {m[1]:.10g} | oracle rmse {r_rmse:.10g} "
+          f"ssim {r_ssim:.10g}", flush=True)
     assert 0 < m[0] and m[1] < 1
-    assert abs(m[0] - r_rmse) <= 1e-3 * r_rmse and abs(m[1] - r_ssim) <= 1e-4
+    # the RMSE measures the reconstructed noise, whose float32 rounding floor is the noise
+    # part's (see test_noise_parity_and_determinism): 1e-4 relative
+    assert abs(m[0] - r_rmse) <= 1e-4 * r_rmse and abs(m[1] - r_ssim) <= 1e-5
 
 
 def test_data_path_full_size_sampled():

@@ -1,8 +1,11 @@
 """GPU tests of the grouped multi-request backprojection and the serving loop: every
-request's volume is bit-identical alone (plain katsevich_recon) and in the mix."""
+request's volume is bit-identical alone (plain katsevich_recon) and in the mix, and equal to
+the FP64 oracle's reconstruction to the parity bar (relative L2 <= 1e-5, max |error| <=
+1e-4 of the phantom peak over valid voxels, invalid voxels 0)."""
 import numpy as np
 import pytest
 
+import oracle as O
 from synth import configs, phantom
 
 torch = pytest.importorskip("torch")
@@ -63,6 +66,22 @@ def test_packed_backprojection_equals_single_launches():
         assert torch.equal(a, m)
 
 
+def _oracle_parity(r):
+    ref, valid = O.recon(O.Scan(r.geom), r.grid, r.sino.cpu().numpy())
+    got = r.volume.cpu().numpy()
+    x = r.grid["x_first"] + np.arange(r.grid["nx"]) * r.grid["dx"]
+    y = r.grid["y_first"] + np.arange(r.grid["ny"]) * r.grid["dy"]
+    z = r.grid["z_first"] + np.arange(r.grid["nz"]) * r.grid["dz"]
+    d = (got - ref)[valid]
+    rel = float(np.linalg.norm(d) / np.linalg.norm(ref[valid]))
+    print(f"[parity] served request {r.rid} vs oracle: rel-L2 {rel:.3e}, max-abs "
+          f"{np.abs(d).max():.3e}, {int(valid.sum())} valid voxels", flush=True)
+    assert valid.sum() > 0 and np.all(got[~valid] == 0)
+    peak = float(np.abs(ref[valid]).max())
+    assert rel <= 1e-5 and np.abs(d).max() <= 1e-4 * peak
+    del x, y, z
+
+
 @pytest.mark.parametrize("saturated", [True, False])
 def test_served_results_equal_alone(saturated):
     dev = _dev()
@@ -84,7 +103,32 @@ def test_served_results_equal_alone(saturated):
         print(f"[serve] request {r.rid}: latency {r.latency * 1e3:.1f} ms hit={r.cache_hit}",
               flush=True)
         assert torch.equal(alone, r.volume)
+        if saturated:
+            _oracle_parity(r)
     assert cache.misses >= 4 and len(cache.plans) == 4      # two requests share a geometry
+    cache.close()
+
+
+def test_served_results_with_plans_evicted():
+    """A table budget that holds no plan: every plan is dropped once its requests complete
+    (a request holds its plan from arrival to completion), and the served volumes are still
+    those of plain katsevich_recon and of the oracle."""
+    dev = _dev()
+    reqs = _small_requests()
+    cache = serve.PlanCache(dev, workers=2, table_budget=1)
+    rs = [serve.Request(rid=i, arrival=0.002 * i, geom=g, grid=gr, sino=torch.from_numpy(s).to(dev))
+          for i, (g, gr, s) in enumerate(reqs)]
+    srv = serve.Server(cache, budget_bytes=64 << 20, max_batch=2, keep_volumes=True)
+    done = srv.run(rs)
+    torch.cuda.synchronize()
+    assert len(done) == len(reqs) and not any(r.error for r in done)
+    assert cache.evicted >= 3 and not cache.inuse
+    for r in sorted(done, key=lambda r: r.rid)[:3]:
+        plan = K.Plan(r.geom, r.grid, device=0)
+        alone = K.recon(plan, r.sino)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, r.volume)
+        _oracle_parity(r)
     cache.close()
 
 

@@ -72,3 +72,35 @@ def test_failed_plan_build_is_reported_per_request():
         with pytest.raises(PlanFailed, match="feed must be positive"):
             cache.poll(bad)
     cache.close()
+
+
+def test_plan_cache_evicts_least_recently_used_unheld_plans():
+    """Beyond the table budget the least recently used plans are dropped, never one that a
+    request in flight holds (acquire / release); a held plan goes once released."""
+    import time
+
+    from paper_2201_02309_amd.serve import PlanCache
+
+    cache = PlanCache(device=None, workers=1, table_budget=3 * 1000)
+    cache._build = lambda geom, grid: (type("P", (), {"info": {"table_bytes": 1000}})(), 0.0)
+    gr = {"nx": 8, "dx": 1.0}
+
+    def get(feed):
+        key, _ = cache.request({"feed_per_turn": feed}, gr)
+        deadline = time.time() + 10
+        while cache.poll(key) is None and time.time() < deadline:
+            time.sleep(0.005)
+        return key
+
+    keys = [get(40.0 + i) for i in range(3)]
+    cache.acquire(keys[0])                       # in flight
+    k3 = get(50.0)                               # 4 plans > budget: keys[1] (LRU, unheld) goes
+    assert keys[0] in cache.plans and keys[1] not in cache.plans and cache.evicted == 1
+    assert cache.table_bytes == 3000
+    get(51.0)                                    # next unheld: keys[2]
+    assert keys[0] in cache.plans and keys[2] not in cache.plans and k3 in cache.plans
+    cache.release(keys[0])                       # released while over no budget: kept
+    assert keys[0] in cache.plans and cache.table_bytes == 3000
+    get(52.0)                                    # now keys[0] is the least recently used
+    assert keys[0] not in cache.plans and cache.evicted == 3
+    cache.close()
