@@ -41,7 +41,7 @@ def _cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(wl, sino_dev, nz_sample=32, iz0=16):
+def cpu_baseline(wl, sino_dev, nz_sample=16, iz0=24):
     """Time the FP64 oracle (oracle.parallel: the oracle's own functions spread over one
     worker process per host core, BLAS limited to one thread each) on a slab of the
     workload: nz_sample consecutive 512 x 512 slices from z index iz0, reconstructed
@@ -317,9 +317,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--network", action="store_true",
-                    help="also time a training step of the dual-domain network (MIOpen compiles "
-                         "its convolutions first: a few minutes on a fresh machine)")
+    ap.add_argument("--no-network", action="store_true",
+                    help="skip the training step of the dual-domain network (MIOpen compiles "
+                         "its convolutions on first use: about two minutes on a fresh machine)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving trace in seconds at 20 requests/s (0 skips it)")
     ap.add_argument("--bp-slices", type=int, default=0,
@@ -343,10 +343,10 @@ def main():
     t0 = time.perf_counter()
     plan = K.Plan(geom, gr, device=0, bp_slices=args.bp_slices)
     t_plan = time.perf_counter() - t0
-    # the same plan with the PI lines solved on the GPU (katsevich_plan_device); warmed once
-    K.Plan(geom, gr, bind=False, gpu_plan=True, device=0, bp_slices=args.bp_slices).close()
+    # the same plan built on the GPU (katsevich_plan_device); warmed once
+    K.Plan(geom, gr, gpu_plan=True, device=0, bp_slices=args.bp_slices).close()
     t0 = time.perf_counter()
-    K.Plan(geom, gr, bind=False, gpu_plan=True, device=0, bp_slices=args.bp_slices).close()
+    K.Plan(geom, gr, gpu_plan=True, device=0, bp_slices=args.bp_slices).close()
     t_plan_gpu = time.perf_counter() - t0
     info = plan.info
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
@@ -452,7 +452,7 @@ def main():
         "adjoint_call_ms": round(adjoint_ms, 3),
         "half_sample_recon_call_ms": round(half_ms, 4),
         "plan_build_s": round(t_plan, 3),
-        "plan_build_gpu_pi_s": round(t_plan_gpu, 3),
+        "plan_build_gpu_s": round(t_plan_gpu, 4),
         "roofline": {"kernel": "k_bp_lds", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
@@ -463,7 +463,8 @@ def main():
     K.recon(plan, K.add_noise(sino, 1e5, 0.5, 3), out=vol, ws=ws)
     out["data_path"] = data_path_bench(sino, vol, ref_vol)
     del ref_vol
-    if args.network:
+    if not args.no_network:
+        print("[bench] dual-domain network training step", file=sys.stderr, flush=True)
         out["network"] = network_bench()
     if args.serve_seconds > 0:
         gF = ws = None
@@ -471,7 +472,7 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = serving_bench(duration=args.serve_seconds)
     if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on a 32-slice slab on every host core "
+        print("[bench] timing the FP64 oracle on a 16-slice slab on every host core "
               "(cpu_baseline)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, sino)
     print(json.dumps(out), flush=True)

@@ -97,3 +97,41 @@ def test_training_step_and_gradient_through_the_layer(sample):
     last = float(L.detach())
     print(f"[network] loss {first:.5g} -> {last:.5g} over 8 Adam steps", flush=True)
     assert last < first
+
+
+def test_layer_inside_the_network_matches_the_oracle(sample):
+    """The domain-transfer layer as the network uses it: KatsevichFn on the sinogram
+    subnetwork's output (a noisy, network-processed window sinogram, not a clean projection)
+    against the FP64 oracle's reconstruction of the same float32 array, element by element;
+    then its backward (the cotangent that reaches the sinogram subnetwork through the layer)
+    against the oracle's transpose of the same image-side cotangent."""
+    import oracle as O
+    from paper_2201_02309_amd import network as N
+    plan, g_in, g_gt, f_gt, gw, _ = sample
+    torch.manual_seed(1)
+    net = N.DualDomainNet(plan).to(g_in.device)
+    gs = net.sino_net(g_in.unsqueeze(1)).squeeze(1).detach()
+    x = gs.clone().requires_grad_(True)
+    f0 = K.KatsevichFn.apply(x.contiguous(), plan)         # the layer, as in DualDomainNet
+    f = net.image_net(f0.unsqueeze(1)).squeeze(1)
+    L = ((f_gt - f) ** 2).sum()
+    f0.retain_grad()
+    L.backward()
+    scan = O.Scan(gw)
+    gr = plan.grid
+    g_np = gs[0].cpu().numpy()
+    ref, valid = O.recon(scan, gr, g_np)
+    got = f0[0].detach().cpu().numpy()
+    d = (got - ref)[valid]
+    peak = float(np.abs(ref[valid]).max())
+    rel = float(np.linalg.norm(d) / np.linalg.norm(ref[valid]))
+    print(f"[parity] network layer forward vs oracle: rel-L2 {rel:.3e}, max-abs "
+          f"{np.abs(d).max():.3e} (peak {peak:.3f}, {int(valid.sum())} valid)", flush=True)
+    assert valid.sum() > 100 and np.all(got[~valid] == 0)
+    assert rel <= 1e-5 and np.abs(d).max() <= 1e-4 * peak
+    fbar = f0.grad[0].double().cpu().numpy()
+    gref = O.recon_T(scan, gr, fbar)
+    ggot = x.grad[0].double().cpu().numpy()
+    relb = float(np.linalg.norm(ggot - gref) / np.linalg.norm(gref))
+    print(f"[parity] network layer backward vs oracle transpose: rel-L2 {relb:.3e}", flush=True)
+    assert relb <= 1e-5
