@@ -81,7 +81,8 @@ typedef struct katsevich_grid {
 /* Plan options.  n_psi: number of kappa-lines sampled uniformly on
  * [-pi/2-alpha_m, pi/2+alpha_m] (eq. FR range; 0 -> 2*det_rows+1; must be >= 3);
  * n_threads: host threads used to build the plan (0 -> all hardware threads);
- * flags: 0 or KATS_FLAG_HALF_SAMPLE_DERIVATIVE (other bits are rejected);
+ * flags: KATS_FLAG_HALF_SAMPLE_DERIVATIVE | KATS_FLAG_DETERMINISTIC_ADJOINT (other bits
+ * are rejected);
  * bp_slices: slices per backprojection register run (0 -> 16, else 8, 16 or 32; a
  * performance knob, results agree to rounding). */
 typedef struct katsevich_options {
@@ -95,6 +96,15 @@ typedef struct katsevich_options {
  * at alpha_{c+1/2} (c < det_cols-1), and every later step runs on that grid; the sinogram
  * and volume buffers keep their shapes.  Needs n_views >= 4 and det_cols >= 3. */
 #define KATS_FLAG_HALF_SAMPLE_DERIVATIVE 1
+
+/* Deterministic adjoint: katsevich_recon_backward accumulates the transposed
+ * backprojection in 64-bit fixed point (integer sums do not depend on the order of the
+ * atomics) with a power-of-two scale chosen per call from max |d_grad_vol| so that no sum
+ * can overflow, then rounds each filtered-data cotangent once to float32: the same bits on
+ * every run (the default accumulates in float64 / float32 atomics, equal to rounding but
+ * not bit-reproducible).  Costs a larger workspace (workspace_bytes includes it) and
+ * time; the forward is unchanged. */
+#define KATS_FLAG_DETERMINISTIC_ADJOINT 2
 
 typedef struct katsevich_plan_s *katsevich_plan_t;
 

@@ -33,15 +33,23 @@ constexpr int kLPT = kLP;         // box columns
 constexpr int kRowT = 66;
 constexpr int kHullT = 1784;
 
-template <int KZ>
+// DET: the deterministic mode's accumulators are 64-bit fixed point (integer adds are
+// associative, so the result does not depend on the order of the atomics).
+template <int KZ, bool DET>
 struct BpTShared {
     static constexpr int NG = KZ / kKG;
     using Word = typename std::conditional<(NG <= 4), unsigned char, unsigned short>::type;
+    using Acc = typename std::conditional<DET, unsigned long long, double>::type;
     static constexpr int kFull = NG <= 4 ? 4 : 8;
-    __attribute__((aligned(16))) double box[2][kRowT * lds_rows<KZ>()];
+    __attribute__((aligned(16))) Acc box[2][kRowT * lds_rows<KZ>()];
     Word words[4][kHullT];
     int red[8];
 };
+
+// v * S rounded to the nearest integer, two's complement (|v| S < 2^62 by the choice of S)
+__device__ inline unsigned long long to_fixed(float v, double S) {
+    return (unsigned long long)__double2ll_rn((double)v * S);
+}
 
 // FB: some box of the plan may exceed the LDS tile; those views scatter their taps
 // straight into g^F-bar with global atomics (the cells the forward's HBM path reads).
@@ -57,12 +65,24 @@ struct BpTShared {
 // an angle of a few cells whose float32 error is ~1e-6 cell, and atan of its small tangent
 // is the odd series through t^11 (remainder below t^13/13: ~1e-17 at the tangents of
 // voxels in the field of view).
-template <int KZ, bool FB>
-__device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *__restrict__ gFbar,
-                         int rows, int cols, long long first_view,
+//
+// DET (deterministic mode): the boxes accumulate 64-bit integers, each contribution v
+// entering as round(v S) (the split between the two columns taken in integers, so that
+// it sums exactly), and g^F-bar is accumulated the same way in a 64-bit buffer (global
+// integer atomics); S = *fscale, a power of two chosen from max |fbar| so that no sum can
+// reach 2^62.  Integer sums do not depend on their order: the result is the same bits on
+// every run.
+template <int KZ, bool FB, bool DET>
+__device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, void *__restrict__ gFout,
+                         const double *__restrict__ fscale, int rows, int cols, long long first_view,
                          const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
                          const float4 *__restrict__ ray_tab, int bxi, int byi, int bz,
-                         BpTShared<KZ> &S) {
+                         BpTShared<KZ, DET> &S) {
+    using Acc = typename BpTShared<KZ, DET>::Acc;
+    typedef __attribute__((address_space(3))) Acc LdsAcc;
+    float *gFbar = static_cast<float *>(gFout);
+    unsigned long long *gFbar64 = static_cast<unsigned long long *>(gFout);
+    const double fx = DET ? *fscale : 0.0;
     static_assert(KZ % kKG == 0 && KZ / kKG <= 8, "groups use 8-bit masks");
     constexpr int kLR = lds_rows<KZ>();
     constexpr int NG = KZ / kKG;
@@ -126,12 +146,12 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
         red[4 + wave] = whi;
     }
     // both box buffers start zeroed (every flush leaves its cells zero again)
-    for (int i = tid; i < 2 * kRowT * kLR; i += kNT) (&box[0][0])[i] = 0.0;
+    for (int i = tid; i < 2 * kRowT * kLR; i += kNT) (&box[0][0])[i] = 0;
     __syncthreads();
     const int mlo = __builtin_amdgcn_readfirstlane(min(min(red[0], red[1]), min(red[2], red[3])));
     const int mhi = __builtin_amdgcn_readfirstlane(max(max(red[4], red[5]), max(red[6], red[7])));
-    using Word = typename BpTShared<KZ>::Word;
-    constexpr int kFull = BpTShared<KZ>::kFull;
+    using Word = typename BpTShared<KZ, DET>::Word;
+    constexpr int kFull = BpTShared<KZ, DET>::kFull;
     // (an empty hull, mlo = INT_MAX > mhi = INT_MIN, takes no words: mhi - mlo would overflow)
     const bool use_words = mlo <= mhi && mhi - mlo < kHullT;
     if (use_words) {
@@ -159,17 +179,19 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     auto fits = [](const BpBox &b) { return !FB || (b.nr <= kLR && b.nc <= kLPT); };
     // flush of view m's box from buffer buf: lanes over 4 rows x 64 columns per pass
     auto flush = [&](int m, const BpBox &b, int buf) {
-        double *bx = box[buf];
-        float *img = gFbar + (size_t)(base + m - first_view) * vstride;
+        LdsAcc *bx = (LdsAcc *)box[buf];
+        const size_t vo = (size_t)(base + m - first_view) * vstride;
         const int cc = tid & 63;
         for (int rr = tid >> 6; rr < b.nr; rr += 4) {
-            double *cell = bx + rr * kRowT + cc;
-            const double v = *cell;
-            if (v != 0.0) {
-                *cell = 0.0;
+            LdsAcc *cell = bx + __mul24(rr, kRowT) + cc;
+            const Acc v = *cell;
+            if (v != 0) {
+                *cell = 0;
                 const int r = b.r0 + rr, c = b.c0 + cc;
-                if ((unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols)
-                    atomicAdd(img + (size_t)r * cols + c, (float)v);
+                if ((unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols) {
+                    if constexpr (DET) atomicAdd(gFbar64 + vo + (size_t)r * cols + c, v);
+                    else atomicAdd(gFbar + vo + (size_t)r * cols + c, (float)v);
+                }
             }
         }
     };
@@ -237,27 +259,42 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
             }
         };
         if (fits(b)) {
-            double *bx = box[buf] + c0;
+            // LDS addresses in 32 bits (the box is shared memory)
+            LdsAcc *bx = (LdsAcc *)box[buf] + c0;
             walk([&](int row, float v) {
                 if (v != 0.0f) {
                     const float v1 = v * tc;
-                    double *cell = bx + row * kRowT;
-                    atomicAdd(cell, (double)(v - v1));
-                    atomicAdd(cell + 1, (double)v1);
+                    LdsAcc *cell = bx + __mul24(row, kRowT);
+                    if constexpr (DET) {
+                        const unsigned long long q = to_fixed(v, fx), q1 = to_fixed(v1, fx);
+                        __hip_atomic_fetch_add(cell, q - q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(cell + 1, q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    } else {
+                        __hip_atomic_fetch_add(cell, (double)(v - v1), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(cell + 1, (double)v1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                 }
             });
         } else {
             // rows and columns relative to the box, which is clipped to the zero-padded
             // detector; cells of the padding are dropped (the forward reads zeros there)
-            float *img = gFbar + (size_t)(base + m - first_view) * vstride;
+            const size_t vo = (size_t)(base + m - first_view) * vstride;
             const int c = b.c0 + c0;
             walk([&](int row, float v) {
                 const int rd = b.r0 + row;
                 if (v != 0.0f && (unsigned)rd < (unsigned)rows) {
                     const float v1 = v * tc;
-                    float *q = img + (size_t)rd * cols;
-                    if ((unsigned)c < (unsigned)cols) atomicAdd(q + c, v - v1);
-                    if ((unsigned)(c + 1) < (unsigned)cols) atomicAdd(q + c + 1, v1);
+                    const size_t q = vo + (size_t)rd * cols;
+                    if constexpr (DET) {
+                        const unsigned long long f = to_fixed(v, fx), f1 = to_fixed(v1, fx);
+                        if ((unsigned)c < (unsigned)cols) atomicAdd(gFbar64 + q + c, f - f1);
+                        if ((unsigned)(c + 1) < (unsigned)cols) atomicAdd(gFbar64 + q + c + 1, f1);
+                    } else {
+                        if ((unsigned)c < (unsigned)cols) atomicAdd(gFbar + q + c, v - v1);
+                        if ((unsigned)(c + 1) < (unsigned)cols) atomicAdd(gFbar + q + c + 1, v1);
+                    }
                 }
             });
         }
@@ -268,27 +305,72 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, float *
     if (mlo <= mhi && fits(prev_b)) flush(mhi, prev_b, (mhi - mlo) & 1);
 }
 
-template <int KZ, bool FB>
+template <int KZ, bool FB, bool DET>
 __global__ __launch_bounds__(kNT) void k_bpT_lds(BpArgs p, const float *__restrict__ fvol,
-                                                 float *__restrict__ gFbar, int rows, int cols,
-                                                 long long first_view,
+                                                 void *__restrict__ gFout,
+                                                 const double *__restrict__ fscale, int rows,
+                                                 int cols, long long first_view,
                                                  const float4 *__restrict__ view_tab,
                                                  const uint2 *__restrict__ box_tab,
                                                  const float4 *__restrict__ ray_tab) {
-    __shared__ BpTShared<KZ> S;
-    bpT_tile<KZ, FB>(p, fvol, gFbar, rows, cols, first_view, view_tab, box_tab, ray_tab, blockIdx.x,
-                     blockIdx.y, blockIdx.z, S);
+    __shared__ BpTShared<KZ, DET> S;
+    bpT_tile<KZ, FB, DET>(p, fvol, gFout, fscale, rows, cols, first_view, view_tab, box_tab, ray_tab,
+                          blockIdx.x, blockIdx.y, blockIdx.z, S);
 }
 
-template <int KZ>
-void launch_bpT(bool fb, dim3 grid, hipStream_t s, const BpArgs &a, const float *gvol, float *gFbar,
-                int rows, int cols, long long first_view, const float4 *view, const uint2 *boxes,
-                const float4 *rays) {
+template <int KZ, bool DET>
+void launch_bpT(bool fb, dim3 grid, hipStream_t s, const BpArgs &a, const float *gvol, void *gFout,
+                const double *fscale, int rows, int cols, long long first_view, const float4 *view,
+                const uint2 *boxes, const float4 *rays) {
     // fb: HBM path for boxes beyond the LDS tile
     if (fb)
-        hipLaunchKernelGGL((k_bpT_lds<KZ, true>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes, rays);
+        hipLaunchKernelGGL((k_bpT_lds<KZ, true, DET>), grid, dim3(kNT), 0, s, a, gvol, gFout, fscale, rows,
+                           cols, first_view, view, boxes, rays);
     else
-        hipLaunchKernelGGL((k_bpT_lds<KZ, false>), grid, dim3(kNT), 0, s, a, gvol, gFbar, rows, cols, first_view, view, boxes, rays);
+        hipLaunchKernelGGL((k_bpT_lds<KZ, false, DET>), grid, dim3(kNT), 0, s, a, gvol, gFout, fscale, rows,
+                           cols, first_view, view, boxes, rays);
+}
+
+// ----------------------------------------------------------------------------- fixed point
+
+// partial maxima of |fbar| (grid-stride)
+__global__ __launch_bounds__(kNT) void k_absmax_partial(const float *__restrict__ x, unsigned long long n,
+                                                        float *__restrict__ part) {
+    __shared__ float sh[kNT / 64];
+    float m = 0.0f;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * kNT + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * kNT)
+        m = fmaxf(m, fabsf(x[i]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+}
+
+// S = 2^e with bound * max|fbar| * S < 2^62 (bound: the largest possible |g^F-bar| cell per
+// unit of max|fbar|); S = 1 when fbar is zero
+__global__ __launch_bounds__(kNT) void k_fixed_scale(const float *__restrict__ part, int np, double bound,
+                                                     double *__restrict__ S) {
+    __shared__ float sh[kNT / 64];
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < np; i += kNT) m = fmaxf(m, part[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mx = (double)fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3])) * bound;
+        *S = mx > 0.0 ? ldexp(1.0, 61 - ilogb(mx)) : 1.0;       // mx S in [2^61, 2^62)
+    }
+}
+
+// g^F-bar = fixed-point sums / S, rounded once to float32
+__global__ __launch_bounds__(kNT) void k_fixed_to_float(const unsigned long long *__restrict__ in,
+                                                        unsigned long long n, const double *__restrict__ S,
+                                                        float *__restrict__ out) {
+    const double inv = 1.0 / *S;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * kNT + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * kNT)
+        out[i] = (float)((double)(long long)in[i] * inv);
 }
 
 }  // namespace
@@ -300,10 +382,49 @@ hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFba
     const float4 *rays = reinterpret_cast<const float4 *>(k.tref);
     const bool fb = !k.bp_all_fit;
     switch (k.bp_kz) {
-        case 8: launch_bpT<8>(fb, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
-        case 32: launch_bpT<32>(fb, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
-        default: launch_bpT<16>(fb, grid, s, a, gvol, gFbar, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        case 8: launch_bpT<8, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        case 32: launch_bpT<32, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        default: launch_bpT<16, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject_T_fixed(const KParams &k, const float *gvol, unsigned long long *gF64,
+                                      void *scratch, double bound, hipStream_t s) {
+    const unsigned long long nvol = (unsigned long long)k.nx * k.ny * k.nz;
+    const unsigned long long ngf = (unsigned long long)k.n_filt * k.rows * k.cols;
+    float *part = static_cast<float *>(scratch);
+    double *S = reinterpret_cast<double *>(static_cast<unsigned char *>(scratch) + (uint64_t)kFixedScaleBlocks * 4);
+    const unsigned long long pb = (nvol + kNT * 16ull - 1) / (kNT * 16ull);
+    const int np = (int)(pb < 1 ? 1 : (pb > (unsigned long long)kFixedScaleBlocks ? kFixedScaleBlocks : pb));
+    hipLaunchKernelGGL(k_absmax_partial, dim3(np), dim3(kNT), 0, s, gvol, nvol, part);
+    hipLaunchKernelGGL(k_fixed_scale, dim3(1), dim3(kNT), 0, s, (const float *)part, np, bound, S);
+    hipError_t e = launch_zero(gF64, ngf * 8, s);
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)k.bp_tiles_x, (unsigned)k.bp_tiles_y, (unsigned)(k.n_pitches * k.bp_runs));
+    const BpArgs a = bp_args(k);
+    const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
+    const float4 *rays = reinterpret_cast<const float4 *>(k.tref);
+    const bool fb = !k.bp_all_fit;
+    switch (k.bp_kz) {
+        case 8: launch_bpT<8, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        case 32: launch_bpT<32, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        default: launch_bpT<16, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+    }
+    return hipGetLastError();
+}
+
+const double *fixed_scale_ptr(const void *scratch) {
+    return reinterpret_cast<const double *>(static_cast<const unsigned char *>(scratch) +
+                                            (uint64_t)kFixedScaleBlocks * 4);
+}
+
+hipError_t launch_fixed_to_float(const unsigned long long *in, unsigned long long n, const double *S,
+                                 float *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned long long cb = (n + kNT - 1) / kNT;
+    hipLaunchKernelGGL(k_fixed_to_float, dim3((unsigned)(cb < 16384 ? cb : 16384)), dim3(kNT), 0, s, in, n, S,
+                       out);
     return hipGetLastError();
 }
 

@@ -102,7 +102,67 @@ KParams make_params(const PlanHost &P) {
     return k;
 }
 
-hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
+// Workspace of katsevich_recon: [g4 chunk | g2 chunk | g^F of every filtered view].
+uint64_t recon_ws(const PlanHost &P) { return P.g4_bytes + P.g2_bytes + P.gF_bytes; }
+
+// Workspace of katsevich_recon_backward: [g4 chunk | g2 chunk | g^F-bar (float or fixed
+// point) | conversion chunk | scale scratch].
+uint64_t backward_ws(const PlanHost &P) {
+    return P.g4_bytes + P.g2_bytes + P.gbar_bytes + P.conv_bytes + P.det_bytes;
+}
+
+// The forward filter chain over chunks of views: g2 / g4 hold one chunk, g^F every view.
+static hipError_t filter_chunks(const PlanHost &P, const KParams &k, const float *sino, float *g2,
+                                float *g4, float *gF, hipStream_t s) {
+    const size_t gfv = (size_t)k.gf_rows * k.gf_cols;
+    for (long long a = 0; a < k.n_filt; a += P.chunk_views) {
+        KParams kc = k;
+        kc.first_view = k.first_view + a;
+        kc.n_filt = std::min<long long>(P.chunk_views, k.n_filt - a);
+        const hipError_t e = launch_filter(kc, sino, g2, g4, gF + (size_t)a * gfv, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// The adjoint filter chain over chunks, each with one view of halo on both sides (the
+// derivative transpose of a sinogram view reads its neighbours); sinogram views no filtered
+// view reaches are zeroed.  g64 / S (deterministic mode): g^F-bar in fixed point, each
+// chunk converted to float into conv first; otherwise gbar is float.
+static hipError_t filter_T_chunks(const PlanHost &P, const KParams &k, const float *gbar,
+                                  const unsigned long long *g64, const double *S, float *conv,
+                                  float *g4, float *g2, float *gsino, hipStream_t s) {
+    const size_t rc = (size_t)k.rows * k.cols;
+    const long long sv = k.half ? k.sino_views : k.n_views;
+    const size_t srow = (size_t)k.rows * (k.half ? k.sino_cols : k.cols) * 4;   // bytes per view
+    const long long n = k.n_filt, fv = k.first_view;
+    long long out_lo = 0, out_hi = 0;
+    if (n > 0) {
+        out_lo = k.half ? fv : fv - 1;
+        out_hi = fv + n + 1;
+    }
+    hipError_t e = hipSuccess;
+    if (out_lo > 0) e = launch_zero(gsino, (uint64_t)out_lo * srow, s);
+    if (e == hipSuccess && out_hi < sv)
+        e = launch_zero(reinterpret_cast<unsigned char *>(gsino) + (size_t)out_hi * srow,
+                        (uint64_t)(sv - out_hi) * srow, s);
+    for (long long a = 0; a < n && e == hipSuccess; a += P.chunk_views) {
+        const long long b = std::min<long long>(n, a + P.chunk_views);
+        const long long a1 = a > 0 ? a - 1 : 0, b1 = b < n ? b + 1 : n;
+        KParams kc = k;
+        kc.first_view = fv + a1;
+        kc.n_filt = b1 - a1;
+        const float *src = gbar + (size_t)a1 * rc;
+        if (g64) {
+            e = launch_fixed_to_float(g64 + (size_t)a1 * rc, (unsigned long long)(b1 - a1) * rc, S, conv, s);
+            src = conv;
+        }
+        if (e == hipSuccess) e = launch_filter_T_views(kc, src, g4, g2, s);
+        const long long lo = a > 0 ? fv + a : out_lo, hi = b < n ? fv + b : out_hi;
+        if (e == hipSuccess) e = launch_deriv_T(kc, g2, gsino, lo, hi - lo, s);
+    }
+    return e;
+}
 
 }  // namespace kats
 
@@ -220,7 +280,7 @@ int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
     const kats::PlanHost &P = plan->P;
     katsevich_plan_info i{};
     i.table_bytes = P.layout.total;
-    i.workspace_bytes = P.g4_bytes + std::max(P.g2_bytes, P.gF_bytes);
+    i.workspace_bytes = kats::recon_ws(P) > kats::backward_ws(P) ? kats::recon_ws(P) : kats::backward_ws(P);
     i.filtered_bytes = P.gF_bytes;
     i.workspace_bytes_filter = P.g4_bytes + P.g2_bytes;
     i.first_view = P.first_view;
@@ -345,7 +405,7 @@ int katsevich_filter(katsevich_plan_t plan, const float *d_sino, float *d_gF, vo
     const kats::KParams k = kats::make_params(P);
     float *g4 = static_cast<float *>(d_ws);
     float *g2 = reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + P.g4_bytes);
-    hipError_t e = kats::launch_filter(k, d_sino, g2, g4, d_gF, static_cast<hipStream_t>(stream));
+    hipError_t e = kats::filter_chunks(P, k, d_sino, g2, g4, d_gF, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "katsevich_filter: launch");
     return KATS_OK;
 }
@@ -366,19 +426,19 @@ int katsevich_recon(katsevich_plan_t plan, const float *d_sino, float *d_vol, vo
     int st = check_compute(plan, d_sino, d_vol, "katsevich_recon");
     if (st) return st;
     const kats::PlanHost &P = plan->P;
-    const uint64_t need = P.g4_bytes + std::max(P.g2_bytes, P.gF_bytes);
+    const uint64_t need = kats::recon_ws(P);
     if (need > 0 && (!d_ws || ws_bytes < need))
         return fail(KATS_EWORKSPACE, "katsevich_recon: workspace too small");
     if (d_ws && !aligned256(d_ws)) return fail(KATS_EINVAL, "katsevich_recon: workspace not 256-byte aligned");
     const kats::KParams k = kats::make_params(P);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    float *g4 = static_cast<float *>(d_ws);
-    float *g2 = reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + P.g4_bytes);
-    // the padded g^F overwrites g2 (consumed by the Hilbert stage before the backward
-    // rebinning runs)
-    hipError_t e = kats::launch_filter(k, d_sino, g2, g4, g2, s);
+    unsigned char *w = static_cast<unsigned char *>(d_ws);
+    float *g4 = reinterpret_cast<float *>(w);
+    float *g2 = reinterpret_cast<float *>(w + P.g4_bytes);
+    float *gF = reinterpret_cast<float *>(w + P.g4_bytes + P.g2_bytes);
+    hipError_t e = kats::filter_chunks(P, k, d_sino, g2, g4, gF, s);
     if (e != hipSuccess) return hip_fail(e, "katsevich_recon: filter launch");
-    e = kats::launch_backproject(k, g2, d_vol, s);
+    e = kats::launch_backproject(k, gF, d_vol, s);
     if (e != hipSuccess) return hip_fail(e, "katsevich_recon: backprojection launch");
     return KATS_OK;
 }
@@ -389,16 +449,34 @@ int katsevich_recon_backward(katsevich_plan_t plan, const float *d_grad_vol, flo
     int st = check_compute(plan, d_grad_vol, d_grad_sino, "katsevich_recon_backward");
     if (st) return st;
     const kats::PlanHost &P = plan->P;
-    if (P.g4_bytes + P.g2_bytes > 0 && (!d_ws || ws_bytes < P.g4_bytes + P.g2_bytes))
+    const uint64_t need = kats::backward_ws(P);
+    if (need > 0 && (!d_ws || ws_bytes < need))
         return fail(KATS_EWORKSPACE, "katsevich_recon_backward: workspace too small");
     if (d_ws && !aligned256(d_ws)) return fail(KATS_EINVAL, "katsevich_recon_backward: workspace not 256-byte aligned");
     const kats::KParams k = kats::make_params(P);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    float *g4 = static_cast<float *>(d_ws);
-    float *g2 = reinterpret_cast<float *>(static_cast<unsigned char *>(d_ws) + P.g4_bytes);
-    hipError_t e = kats::launch_zero(g2, P.g2_bytes, s);
-    if (e == hipSuccess) e = kats::launch_backproject_T(k, d_grad_vol, g2, s);
-    if (e == hipSuccess) e = kats::launch_filter_T(k, g2, g4, g2, d_grad_sino, s);
+    unsigned char *w = static_cast<unsigned char *>(d_ws);
+    float *g4 = reinterpret_cast<float *>(w);
+    float *g2 = reinterpret_cast<float *>(w + P.g4_bytes);
+    void *gbar = w + P.g4_bytes + P.g2_bytes;
+    hipError_t e = hipSuccess;
+    if (P.det_adjoint) {
+        // bound: every valid voxel adding at most max|fbar| dlambda/(2 pi) / v* to a cell,
+        // v* >= R - r_fov for voxels in the field of view
+        float *conv = reinterpret_cast<float *>(w + P.g4_bytes + P.g2_bytes + P.gbar_bytes);
+        void *scr = w + P.g4_bytes + P.g2_bytes + P.gbar_bytes + P.conv_bytes;
+        const double bound = (double)std::max<int64_t>(P.n_valid, 1) * (P.dlam / (2.0 * 3.14159265358979323846)) /
+                             (P.geom.R - P.r_fov);
+        unsigned long long *g64 = static_cast<unsigned long long *>(gbar);
+        e = kats::launch_backproject_T_fixed(k, d_grad_vol, g64, scr, bound, s);
+        if (e == hipSuccess)
+            e = kats::filter_T_chunks(P, k, nullptr, g64, kats::fixed_scale_ptr(scr), conv, g4, g2, d_grad_sino, s);
+    } else {
+        float *gb = static_cast<float *>(gbar);
+        e = kats::launch_zero(gb, P.gbar_bytes, s);
+        if (e == hipSuccess) e = kats::launch_backproject_T(k, d_grad_vol, gb, s);
+        if (e == hipSuccess) e = kats::filter_T_chunks(P, k, gb, nullptr, nullptr, nullptr, g4, g2, d_grad_sino, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "katsevich_recon_backward: launch");
     return KATS_OK;
 }

@@ -450,8 +450,8 @@ __global__ __launch_bounds__(kColWave) void k_fr_lw_T(KParams p, const float *__
 //   (g2bar[n-1] - g2bar[n+1]) / (2 dlambda) + (g2bar[c-1] - g2bar[c+1]) / (2 dalpha)
 // over the filtered views (views outside contribute 0).  Every sinogram sample is written.
 __global__ __launch_bounds__(kElemThreads) void k_deriv_T(KParams p, const float *__restrict__ g2bar,
-                                                          float *__restrict__ gsino) {
-    const long long n = blockIdx.x;                 // every sinogram view
+                                                          float *__restrict__ gsino, long long n0) {
+    const long long n = n0 + blockIdx.x;            // sinogram view
     const int r = blockIdx.y;
     const int c = blockIdx.z * kElemThreads + threadIdx.x;
     if (c >= p.cols) return;
@@ -469,8 +469,8 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_T(KParams p, const float
 // Transpose of the half-sample derivative (LW^T is applied by k_fr_lw_T): sinogram
 // sample (n, r, c) belongs to the cells (n-1 .. n) x (c-1 .. c) of the filtered grid.
 __global__ __launch_bounds__(kElemThreads) void k_deriv_T_half(KParams p, const float *__restrict__ g2bar,
-                                                               float *__restrict__ gsino) {
-    const long long n = blockIdx.x;                 // every sinogram view
+                                                               float *__restrict__ gsino, long long n0) {
+    const long long n = n0 + blockIdx.x;            // sinogram view
     const int r = blockIdx.y;
     const int c = blockIdx.z * kElemThreads + threadIdx.x;
     if (c >= p.sino_cols) return;
@@ -503,26 +503,37 @@ hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *
     return hipGetLastError();
 }
 
-hipError_t launch_filter_T(const KParams &k, const float *gFbar, float *g4bar, float *g2bar,
-                           float *gsino, hipStream_t s) {
+hipError_t launch_filter_T_views(const KParams &k, const float *gFbar, float *g4bar, float *g2bar,
+                                 hipStream_t s) {
+    if (k.n_filt <= 0) return hipSuccess;
     const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
-    if (k.n_filt > 0) {
-        const unsigned cw = (unsigned)((k.cols + kColWave - 1) / kColWave);
-        hipLaunchKernelGGL(k_br_cos_T, dim3((unsigned)k.n_filt, cb), dim3(kElemThreads), 0, s, k,
-                           gFbar, g4bar);
-        launch_hilbert<true>(k, nullptr, g4bar, s);
-        hipLaunchKernelGGL(k_fr_lw_T, dim3((unsigned)k.n_filt, cw), dim3(kColWave), 0, s, k,
-                           g4bar, g2bar);
-    }
+    const unsigned cw = (unsigned)((k.cols + kColWave - 1) / kColWave);
+    hipLaunchKernelGGL(k_br_cos_T, dim3((unsigned)k.n_filt, cb), dim3(kElemThreads), 0, s, k, gFbar, g4bar);
+    launch_hilbert<true>(k, nullptr, g4bar, s);
+    hipLaunchKernelGGL(k_fr_lw_T, dim3((unsigned)k.n_filt, cw), dim3(kColWave), 0, s, k, g4bar, g2bar);
+    return hipGetLastError();
+}
+
+hipError_t launch_deriv_T(const KParams &k, const float *g2bar, float *gsino, long long n0,
+                          long long count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
     if (k.half) {
         const int cbs = (k.sino_cols + kElemThreads - 1) / kElemThreads;
-        hipLaunchKernelGGL(k_deriv_T_half, dim3((unsigned)k.sino_views, k.rows, cbs), dim3(kElemThreads),
-                           0, s, k, g2bar, gsino);
+        hipLaunchKernelGGL(k_deriv_T_half, dim3((unsigned)count, k.rows, cbs), dim3(kElemThreads), 0, s, k,
+                           g2bar, gsino, n0);
     } else {
-        hipLaunchKernelGGL(k_deriv_T, dim3((unsigned)k.n_views, k.rows, cb), dim3(kElemThreads), 0, s,
-                           k, g2bar, gsino);
+        const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
+        hipLaunchKernelGGL(k_deriv_T, dim3((unsigned)count, k.rows, cb), dim3(kElemThreads), 0, s, k, g2bar,
+                           gsino, n0);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_filter_T(const KParams &k, const float *gFbar, float *g4bar, float *g2bar,
+                           float *gsino, hipStream_t s) {
+    hipError_t e = launch_filter_T_views(k, gFbar, g4bar, g2bar, s);
+    if (e != hipSuccess) return e;
+    return launch_deriv_T(k, g2bar, gsino, 0, k.half ? k.sino_views : k.n_views, s);
 }
 
 }  // namespace kats

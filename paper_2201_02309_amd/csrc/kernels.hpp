@@ -74,8 +74,26 @@ hipError_t launch_backproject_batch(const KParams *ks, const float *const *gF, f
                                     int n, int kz, hipStream_t s);
 // Adjoint pieces.
 hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFbar, hipStream_t s);
+// Deterministic adjoint backprojection: max |gvol| -> power-of-two scale S (bound * max * S
+// < 2^62) kept in the scratch (fixed_scale_ptr), 64-bit fixed-point accumulation into gF64
+// (zeroed here); launch_fixed_to_float turns a range of it into g^F-bar = gF64 / S.
+constexpr int kFixedScaleBlocks = 4096;     // partial maxima of the scale reduction
+inline uint64_t fixed_scratch_bytes() { return (uint64_t)kFixedScaleBlocks * 4 + 256; }
+hipError_t launch_backproject_T_fixed(const KParams &k, const float *gvol, unsigned long long *gF64,
+                                      void *scratch, double bound, hipStream_t s);
+const double *fixed_scale_ptr(const void *scratch);
+hipError_t launch_fixed_to_float(const unsigned long long *in, unsigned long long n, const double *S,
+                                 float *out, hipStream_t s);
+hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
 hipError_t launch_filter_T(const KParams &k, const float *gFbar, float *g4bar, float *g2bar,
                            float *gsino, hipStream_t s);
+// The per-view transposes (BR^T + cos, Hilbert^T, FR^T + LW) of views first_view ..
+// first_view + n_filt - 1 of k, and the derivative transpose of sinogram views n0 ..
+// n0 + count - 1 from the g2bar of k's views (zero outside them).
+hipError_t launch_filter_T_views(const KParams &k, const float *gFbar, float *g4bar, float *g2bar,
+                                 hipStream_t s);
+hipError_t launch_deriv_T(const KParams &k, const float *g2bar, float *gsino, long long n0,
+                          long long count, hipStream_t s);
 
 // ---- Device plan builder (plan_gpu.hip): float64 scalars of the plan, exactly as the host
 // builder holds them.

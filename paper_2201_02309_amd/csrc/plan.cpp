@@ -281,7 +281,9 @@ static int table_slices(const katsevich_geometry &g, const katsevich_grid &gr, i
 static int plan_setup(const katsevich_geometry &g_in, const katsevich_grid &gr,
                       const katsevich_options &opts, PlanHost &P, std::string &err) {
     auto bad = [&](const std::string &m) { err = m; return KATS_EINVAL_GEOMETRY; };
-    if (opts.flags & ~KATS_FLAG_HALF_SAMPLE_DERIVATIVE) return bad("unknown option flags");
+    if (opts.flags & ~(KATS_FLAG_HALF_SAMPLE_DERIVATIVE | KATS_FLAG_DETERMINISTIC_ADJOINT))
+        return bad("unknown option flags");
+    P.det_adjoint = (opts.flags & KATS_FLAG_DETERMINISTIC_ADJOINT) != 0;
     // Half-sample derivative: eq. Deriv is taken at the centre of each 2 x 2 cell of the
     // sinogram's (lambda, alpha) samples, so the filtered data live on views lambda_{n+1/2}
     // and columns alpha_{c+1/2}: one view and one column fewer, the same column offset
@@ -405,9 +407,15 @@ static void make_layout(PlanHost &P, int W) {
 static void set_workspace(PlanHost &P) {
     const katsevich_geometry &g = P.geom;
     const int64_t nfilt = std::max<int64_t>(0, P.last_view - P.first_view + 1);
-    P.g4_bytes = align256((uint64_t)nfilt * P.n_psi * g.det_cols * 4);
-    P.g2_bytes = align256((uint64_t)nfilt * g.det_rows * g.det_cols * 4);
+    const uint64_t rc = (uint64_t)g.det_rows * g.det_cols;
+    P.chunk_views = std::min<int64_t>(nfilt, kFilterChunk);
+    const uint64_t cv = nfilt > 0 ? (uint64_t)P.chunk_views + 2 : 0;     // + the adjoint's halo
+    P.g4_bytes = align256(cv * P.n_psi * g.det_cols * 4);
+    P.g2_bytes = align256(cv * rc * 4);
     P.gF_bytes = align256((uint64_t)nfilt * P.gf_rows * P.gf_cols * 4);
+    P.gbar_bytes = align256((uint64_t)nfilt * rc * (P.det_adjoint ? 8 : 4));
+    P.conv_bytes = P.det_adjoint ? align256(cv * rc * 4) : 0;
+    P.det_bytes = P.det_adjoint ? align256(fixed_scratch_bytes()) : 0;
 }
 
 int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,

@@ -37,6 +37,9 @@ constexpr int kPad = 2;
 // boxes all fit lets the kernel drop its HBM fallback path.
 constexpr int kBpBoxRows = 32;
 constexpr int kBpBoxCols = 64;
+// Views per chunk of the filter chains (bounds their intermediates: 512 views of the
+// clinical detector take 0.19 GB of kappa-rows).
+constexpr int kFilterChunk = 512;
 
 // Detector footprint (absolute row/col origin, may be -kPad, and extent) of one
 // backprojection tile x slice run at one pitch-relative view: every bilinear tap of
@@ -132,8 +135,16 @@ struct PlanHost {
     float atan_coef[9] = {0};
     int atan_deg = -1;
 
-    // workspace layout (bytes)
-    uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0;   // gF: padded [n][rows+2kPad][cols+2kPad]
+    // workspace layout (bytes).  The filter chains run over chunks of at most chunk_views
+    // views (plus one view each side for the adjoint's derivative): g4 and g2 hold one
+    // chunk's kappa-rows and detector rows; gF the padded g^F of every filtered view
+    // [n][rows+2kPad][cols+2kPad]; gbar the adjoint's g^F-bar of every filtered view (float,
+    // or 64-bit fixed point in the deterministic mode, which also takes conv_bytes for one
+    // chunk's conversion to float and det_bytes of scale scratch).
+    int64_t chunk_views = 0;
+    uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0, gbar_bytes = 0;
+    bool det_adjoint = false;                           // KATS_FLAG_DETERMINISTIC_ADJOINT
+    uint64_t conv_bytes = 0, det_bytes = 0;
 };
 
 // Build the plan on the host in float64; returns a KATS_* status and fills err on failure.

@@ -62,6 +62,7 @@ class _Info(ctypes.Structure):
 
 
 FLAG_HALF_SAMPLE_DERIVATIVE = 1   # KATS_FLAG_HALF_SAMPLE_DERIVATIVE (include/katsevich.h)
+FLAG_DETERMINISTIC_ADJOINT = 2    # KATS_FLAG_DETERMINISTIC_ADJOINT
 
 # table id -> (C enum, numpy dtype, shape key)
 TABLES = {
@@ -172,13 +173,15 @@ class Plan:
 
     def __init__(self, geom: dict, grid: dict, n_psi: int = 0, n_threads: int = 0,
                  bind: bool = True, device=None, bp_slices: int = 0, gpu_plan: bool = False,
-                 half_sample: bool = False, keep_pi_scratch: bool = False):
+                 half_sample: bool = False, keep_pi_scratch: bool = False,
+                 deterministic_adjoint: bool = False):
         """gpu_plan: build the whole plan on the GPU (katsevich_plan_device) on `device` and
         its current stream, straight into the plan's table tensor (the plan is then bound
         whatever `bind` says); otherwise on the host (katsevich_plan).  keep_pi_scratch
         (gpu_plan only): keep the build's scratch, whose float64 PI tables pi_tables() reads.
         half_sample: KATS_FLAG_HALF_SAMPLE_DERIVATIVE (derivative at the centres of the
-        sinogram's 2 x 2 (lambda, alpha) cells)."""
+        sinogram's 2 x 2 (lambda, alpha) cells).  deterministic_adjoint:
+        KATS_FLAG_DETERMINISTIC_ADJOINT (bit-reproducible recon_backward)."""
         self._lib = load_library()
         self.geom = dict(geom)
         self.grid = dict(grid)
@@ -188,7 +191,8 @@ class Plan:
         self.device = None
         self._pi_scratch = None
         opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads),
-                        flags=FLAG_HALF_SAMPLE_DERIVATIVE if half_sample else 0,
+                        flags=(FLAG_HALF_SAMPLE_DERIVATIVE if half_sample else 0) |
+                        (FLAG_DETERMINISTIC_ADJOINT if deterministic_adjoint else 0),
                         bp_slices=int(bp_slices))
         g, gr = _geom_struct(geom), _grid_struct(grid)
         if gpu_plan:
