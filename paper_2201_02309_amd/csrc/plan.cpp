@@ -408,7 +408,8 @@ static void set_workspace(PlanHost &P) {
     const katsevich_geometry &g = P.geom;
     const int64_t nfilt = std::max<int64_t>(0, P.last_view - P.first_view + 1);
     const uint64_t rc = (uint64_t)g.det_rows * g.det_cols;
-    P.chunk_views = std::min<int64_t>(nfilt, kFilterChunk);
+    const uint64_t per_view = (uint64_t)(P.n_psi + g.det_rows) * g.det_cols * 4;
+    P.chunk_views = std::min<int64_t>(nfilt, std::max<int64_t>(kFilterChunk, (int64_t)(kFilterChunkBytes / per_view)));
     const uint64_t cv = nfilt > 0 ? (uint64_t)P.chunk_views + 2 : 0;     // + the adjoint's halo
     P.g4_bytes = align256(cv * P.n_psi * g.det_cols * 4);
     P.g2_bytes = align256(cv * rc * 4);

@@ -37,9 +37,12 @@ constexpr int kPad = 2;
 // boxes all fit lets the kernel drop its HBM fallback path.
 constexpr int kBpBoxRows = 32;
 constexpr int kBpBoxCols = 64;
-// Views per chunk of the filter chains (bounds their intermediates: 512 views of the
-// clinical detector take 0.19 GB of kappa-rows).
+// Views per chunk of the filter chains: as many as kFilterChunkBytes of intermediates
+// (kappa-rows + detector rows) hold, at least kFilterChunk (512 views of the clinical
+// 736-column detector take 0.29 GB; a narrow detector gets longer chunks, whose launches
+// would otherwise be too short to fill the GPU).
 constexpr int kFilterChunk = 512;
+constexpr uint64_t kFilterChunkBytes = 256ull << 20;
 
 // Detector footprint (absolute row/col origin, may be -kPad, and extent) of one
 // backprojection tile x slice run at one pitch-relative view: every bilinear tap of
