@@ -211,23 +211,37 @@ def test_long_hulls_take_the_exact_fallback():
 def test_grid_beyond_the_scan_reconstructs_to_zero(dz_mm):
     """Degenerate plan: the grid lies above (or below) every slice the helix covers, so no
     voxel is valid and no view is filtered; recon writes zeros over a volume that held other
-    values, and the adjoint writes zeros over the whole sinogram."""
+    values, and the adjoint (float and deterministic) writes zeros over the whole sinogram;
+    the plan built on the GPU says the same."""
     dev = _dev()
     wl = configs.config1()
     geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
     gr["z_first"] += dz_mm
     print(f"[case] grid beyond the scan, z shifted {dz_mm} mm", flush=True)
-    plan = K.Plan(geom, gr, device=0)
-    assert plan.info["n_vv"] == 0 and plan.n_filtered == 0
-    assert not plan.export("valid").any()
-    g = torch.rand((geom["n_views"], geom["det_rows"], geom["det_cols"]), device=dev,
-                   generator=torch.Generator(dev).manual_seed(5))
-    vol = torch.full((gr["nz"], gr["ny"], gr["nx"]), 7.0, device=dev)
-    K.recon(plan, g, out=vol)
-    gs = torch.full_like(g, 7.0)
-    K.recon_backward(plan, torch.rand_like(vol), out=gs)
-    torch.cuda.synchronize()
-    assert int(torch.count_nonzero(vol)) == 0 and int(torch.count_nonzero(gs)) == 0
+    for kw in ({}, {"gpu_plan": True}, {"deterministic_adjoint": True}):
+        plan = K.Plan(geom, gr, device=0, **kw)
+        assert plan.info["n_vv"] == 0 and plan.n_filtered == 0
+        assert not plan.export("valid").any()
+        g = torch.rand((geom["n_views"], geom["det_rows"], geom["det_cols"]), device=dev,
+                       generator=torch.Generator(dev).manual_seed(5))
+        vol = torch.full((gr["nz"], gr["ny"], gr["nx"]), 7.0, device=dev)
+        K.recon(plan, g, out=vol)
+        gs = torch.full_like(g, 7.0)
+        K.recon_backward(plan, torch.rand_like(vol), out=gs)
+        torch.cuda.synchronize()
+        assert int(torch.count_nonzero(vol)) == 0 and int(torch.count_nonzero(gs)) == 0
+
+
+def test_device_plan_rejects_a_grid_outside_the_field_of_view():
+    """No voxel inside the field of view: the device builder refuses the plan, like the host
+    builder."""
+    _dev()
+    wl = configs.config1()
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    gr = dict(gr, nx=4, ny=4, x_first=200.0, y_first=200.0)        # r > r_fov = 53 mm
+    for kw in ({}, {"gpu_plan": True}):
+        with pytest.raises(K.KatsevichError, match="field of view"):
+            K.Plan(geom, gr, device=0, **kw)
 
 
 def test_turn_shift_gives_pitch_shift_bit_exact():
