@@ -86,8 +86,20 @@ typedef struct katsevich_grid {
  * bp_slices: slices per backprojection register run (0 -> 16, else 8, 16 or 32; a
  * performance knob, results agree to rounding). */
 typedef struct katsevich_options {
-    int32_t n_psi, n_threads, flags, bp_slices;
+    int32_t n_psi, n_threads, flags, bp_slices, hilbert_mode;
 } katsevich_options;
+
+/* hilbert_mode: how the Hilbert filter (eq. HF) of katsevich_filter / katsevich_recon runs.
+ * KATS_HILBERT_AUTO (0) picks KATS_HILBERT_FFT; KATS_HILBERT_FFT (1): zero-padded linear
+ * convolution by register FFTs (float32); KATS_HILBERT_MFMA (2): the same convolution as a
+ * dense Toeplitz product on the matrix cores (even and odd output columns from the odd and
+ * even inputs, float32 operands split into float16 pairs with power-of-two range scaling per
+ * group of kappa rows, float32 accumulation; agrees with the FFT to ~2.5e-7 relative, and
+ * costs a forward-rebinning pass of its own).  The adjoint (katsevich_recon_backward) always
+ * uses the FFT.  Other values: KATS_EINVAL_GEOMETRY. */
+#define KATS_HILBERT_AUTO 0
+#define KATS_HILBERT_FFT 1
+#define KATS_HILBERT_MFMA 2
 
 /* Derivative at constant direction (eq. Deriv) taken at the centre of every 2 x 2 cell of
  * (lambda, alpha) samples instead of by central differences at the samples: each partial
@@ -132,6 +144,8 @@ typedef struct katsevich_plan_info {
                                           last_view, window_lo and the g^F views then count
                                           the cell-centre views lambda_{n+1/2}, and g^F has
                                           det_cols-1 columns */
+    int32_t hilbert_mode;              /* the Hilbert path the plan runs: KATS_HILBERT_FFT or
+                                          KATS_HILBERT_MFMA */
 } katsevich_plan_info;
 
 /* Table ids for katsevich_plan_export (host copies, for tests). */

@@ -23,7 +23,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 SOURCES = [("plan.cpp", False), ("capi.cpp", False), ("filter.hip", True), ("bp.hip", True),
-           ("bp_adjoint.hip", True), ("plan_gpu.hip", True), ("data.hip", True)]
+           ("bp_adjoint.hip", True), ("plan_gpu.hip", True), ("data.hip", True),
+           ("hilbert_mfma.hip", True)]
 
 
 def _run(cmd):

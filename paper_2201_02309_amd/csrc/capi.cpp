@@ -87,6 +87,10 @@ KParams make_params(const PlanHost &P) {
     k.cos_alpha = reinterpret_cast<const float *>(base + L.cos_alpha);
     k.twiddle = reinterpret_cast<const float2 *>(base + L.twiddle);
     k.hil_im = reinterpret_cast<const float *>(base + L.hil_im);
+    k.hil_u = reinterpret_cast<const float *>(base + L.hil_u);
+    k.hil_uinv = (float)(1.0 / kHilTapScale);
+    k.hil_f = P.hil_f;
+    k.hil_mode = P.hil_mode;
     k.pi = reinterpret_cast<const PiEntry *>(base + L.pi);
     k.boxes = reinterpret_cast<const BpBox *>(base + L.boxes);
     k.tref = reinterpret_cast<const TileRay *>(base + L.tref);
@@ -119,7 +123,8 @@ static hipError_t filter_chunks(const PlanHost &P, const KParams &k, const float
         KParams kc = k;
         kc.first_view = k.first_view + a;
         kc.n_filt = std::min<long long>(P.chunk_views, k.n_filt - a);
-        const hipError_t e = launch_filter(kc, sino, g2, g4, gF + (size_t)a * gfv, s);
+        float *vmax = reinterpret_cast<float *>(reinterpret_cast<unsigned char *>(g2) + P.vmax_off);
+        const hipError_t e = launch_filter(kc, sino, g2, g4, gF + (size_t)a * gfv, vmax, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -295,6 +300,7 @@ int katsevich_plan_query(katsevich_plan_t plan, katsevich_plan_info *out) {
     i.window_lo = P.n_lo;
     i.fft_len = P.fft_len;
     i.commensurate = P.commensurate ? 1 : 0;
+    i.hilbert_mode = P.hil_mode;
     i.gf_rows = P.gf_rows;
     i.gf_cols = P.gf_cols;
     i.atan_degree = P.atan_deg;

@@ -362,6 +362,52 @@ void launch_hilbert(const KParams &k, const float *g2, float *g4, hipStream_t s)
     }
 }
 
+// Forward height rebinning alone (eq. FR), for the matrix-core Hilbert: one thread per
+// (view, column, group of kRebinLines kappa lines) forms g3[i][k][c] = (1 - t) g2[i][r0][c] +
+// t g2[i][r0+1][c] for the group's lines, all loads issued before the first use (coalesced
+// over the block's columns; the view's g2 stays in the cache), and the block's max |g3| goes
+// to vmax[i][group][column block], the Hilbert's range scale.
+__global__ __launch_bounds__(kDRThreads) void k_rebin(KParams p, const float *__restrict__ g2,
+                                                      float *__restrict__ g3, float *__restrict__ vmax) {
+    const long long i = blockIdx.x;                    // filtered view of the chunk
+    const int c = blockIdx.y * kDRThreads + threadIdx.x;
+    const int k0 = blockIdx.z * kRebinLines;
+    const int rows = p.rows, cols = p.cols;
+    float mx = 0.0f;
+    if (c < cols) {
+        const float *v2 = g2 + (size_t)i * rows * cols + c;
+        float *out = g3 + (size_t)i * p.n_psi * cols + c;
+        const FrEntry *fr = p.fr + c;
+        FrEntry e[kRebinLines];
+#pragma unroll
+        for (int j = 0; j < kRebinLines; ++j)
+            e[j] = k0 + j < p.n_psi ? fr[(k0 + j) * cols] : FrEntry{-2, 0.0f};
+        float x0[kRebinLines], x1[kRebinLines];
+#pragma unroll
+        for (int j = 0; j < kRebinLines; ++j) {
+            x0[j] = (e[j].r0 >= 0 && e[j].r0 < rows) ? v2[e[j].r0 * cols] : 0.0f;
+            x1[j] = (e[j].r0 + 1 >= 0 && e[j].r0 + 1 < rows) ? v2[(e[j].r0 + 1) * cols] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < kRebinLines; ++j) {
+            if (k0 + j < p.n_psi) {
+                const float v = (1.0f - e[j].w) * x0[j] + e[j].w * x1[j];
+                out[(size_t)(k0 + j) * cols] = v;
+                mx = fmaxf(mx, fabsf(v));
+            }
+        }
+    }
+    __shared__ float red[kDRThreads / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kDRThreads / 64; ++w) mx = fmaxf(mx, red[w]);
+        vmax[(i * gridDim.z + blockIdx.z) * gridDim.y + blockIdx.y] = mx;
+    }
+}
+
 // Writes the zero-padded view [gf_rows][gf_cols] (border = 0).  One thread per (view,
 // padded column, block of rows) walks its rows: successive rows use neighbouring
 // kappa-lines of the same column (psi_hat rises with w), which the cache keeps, so g4 is
@@ -497,7 +543,7 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_T_half(KParams p, const 
 }  // namespace
 
 hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,
-                         hipStream_t s) {
+                         float *vmax, hipStream_t s) {
     if (k.n_filt <= 0) return hipSuccess;
     const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
     const unsigned runs = (unsigned)((k.n_filt + kDerivRun - 1) / kDerivRun);
@@ -505,7 +551,15 @@ hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *
         hipLaunchKernelGGL(k_deriv_lw_half, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
     else
         hipLaunchKernelGGL(k_deriv_lw, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
-    launch_hilbert<false>(k, g2, g4, s);
+    if (k.hil_mode == KATS_HILBERT_MFMA) {
+        const dim3 grid((unsigned)k.n_filt, (unsigned)((k.cols + kDRThreads - 1) / kDRThreads),
+                        (unsigned)((k.n_psi + kRebinLines - 1) / kRebinLines));
+        hipLaunchKernelGGL(k_rebin, grid, dim3(kDRThreads), 0, s, k, g2, g4, vmax);
+        const hipError_t e = launch_hilbert_mfma(k, g4, vmax, s);
+        if (e != hipSuccess) return e;
+    } else {
+        launch_hilbert<false>(k, g2, g4, s);
+    }
     const int cbp = (k.gf_cols + kElemThreads - 1) / kElemThreads;
     hipLaunchKernelGGL(k_br_cos, dim3((unsigned)k.n_filt, cbp, kBrBlocks), dim3(kElemThreads), 0, s, k, g4, gF);
     return hipGetLastError();

@@ -37,6 +37,11 @@ struct KParams {
     const float *cos_alpha;
     const float2 *twiddle;
     const float *hil_im;
+    // Hilbert on the matrix cores (hil_mode 2): reversed odd taps times 2^14 (256 hil_f + 32
+    // floats), 2^-14, 32-column fragments per wave quarter
+    const float *hil_u;
+    float hil_uinv;
+    int hil_f, hil_mode;
     const PiEntry *pi;
     const BpBox *boxes;
     const TileRay *tref;
@@ -62,10 +67,23 @@ hipError_t launch_rmse_ssim(const float *f, const float *g, unsigned long long n
 // scratch; the address is looked up with hipGetSymbolAddress on a device's first call.
 hipError_t static_scratch(void **out, uint64_t *bytes);
 
+// Hilbert filter on the matrix cores, in place on the rebinned kappa rows g4 (vmax: the
+// per-(view, column block) maxima above).
+hipError_t launch_hilbert_mfma(const KParams &k, float *g4, const float *vmax, hipStream_t s);
+
 // Forward filter chain on views first_view..last_view:
 //   g2 = deriv+LW(sino); g4 = Hilbert(FR(g2)); gF = cos * BR(g4).
+// Matrix-core Hilbert path: the forward rebinning runs as a kernel of its own (one thread per
+// (view, column, group of kRebinLines kappa lines)) and leaves one max |g3| per (view, line
+// group, block of kDRThreads columns) for the Hilbert's range scaling.
+constexpr int kDRThreads = 128;
+constexpr int kRebinLines = 16;
+inline uint64_t rebin_max_count(long long n_filt, int n_psi, int cols) {
+    return (uint64_t)n_filt * ((n_psi + kRebinLines - 1) / kRebinLines) * ((cols + kDRThreads - 1) / kDRThreads);
+}
+// vmax: those maxima (MFMA path only).
 hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,
-                         hipStream_t s);
+                         float *vmax, hipStream_t s);
 // Backprojection of every pitch (reusing the first pitch's tables).
 hipError_t launch_backproject(const KParams &k, const float *gF, float *vol, hipStream_t s);
 // Grouped backprojection of n bound plans (one launch per group of up to 16 plans, the
@@ -106,6 +124,7 @@ struct DevPlanArgs {
     int cols, rows, n_psi, fft_len;
     int nx, ny, nz, n_tab, ns, Nv;
     int tiles_x, tiles_y, runs, kz, W_cap;
+    int hil_f;
 };
 
 // Counts the device builder reduces (in scratch; read back once at the end).
@@ -134,6 +153,7 @@ struct DevPlanPtrs {
     float *t_br_w, *lw, *cos_alpha;
     float2 *twiddle;
     float *hil_im;
+    float *hil_u;
     PiEntry *pi;
     BpBox *boxes;
     TileRay *tref;

@@ -317,6 +317,12 @@ static int plan_setup(const katsevich_geometry &g_in, const katsevich_grid &gr,
     if (opts.bp_slices != 0 && opts.bp_slices != 8 && opts.bp_slices != 16 && opts.bp_slices != 32)
         return bad("bp_slices must be 0, 8, 16 or 32");
     P.bp_kz = opts.bp_slices ? opts.bp_slices : kBpKZ;
+    if (opts.hilbert_mode < KATS_HILBERT_AUTO || opts.hilbert_mode > KATS_HILBERT_MFMA)
+        return bad("hilbert_mode must be 0 (auto), 1 (FFT) or 2 (matrix cores)");
+    // auto: the register FFT, measured faster than the matrix-core product on the clinical
+    // workload (filter 2.16 against 2.34 ms)
+    P.hil_mode = opts.hilbert_mode == KATS_HILBERT_MFMA ? KATS_HILBERT_MFMA : KATS_HILBERT_FFT;
+    P.hil_f = ((g.det_cols + 1) / 2 + 127) / 128;            // <= 4 for det_cols <= 1024
 
     const int cols = g.det_cols, rows = g.det_rows;
     P.h = g.feed_per_turn / kTwoPi;
@@ -397,6 +403,7 @@ static void make_layout(PlanHost &P, int W) {
     L.cos_alpha = take((uint64_t)g.det_cols * 4);
     L.twiddle = take((uint64_t)P.fft_len * 8);
     L.hil_im = take((uint64_t)P.fft_len * 4);
+    L.hil_u = take((uint64_t)(256 * P.hil_f + 32) * 4);
     L.pi = take(nvox * sizeof(PiEntry));
     L.boxes = take((uint64_t)P.bp_runs * P.bp_tiles_y * P.bp_tiles_x * W * sizeof(BpBox));
     L.tref = take((uint64_t)P.bp_tiles_y * P.bp_tiles_x * W * sizeof(TileRay));
@@ -412,7 +419,8 @@ static void set_workspace(PlanHost &P) {
     P.chunk_views = std::min<int64_t>(nfilt, std::max<int64_t>(kFilterChunk, (int64_t)(kFilterChunkBytes / per_view)));
     const uint64_t cv = nfilt > 0 ? (uint64_t)P.chunk_views + 2 : 0;     // + the adjoint's halo
     P.g4_bytes = align256(cv * P.n_psi * g.det_cols * 4);
-    P.g2_bytes = align256(cv * rc * 4);
+    P.vmax_off = align256(cv * rc * 4);                 // then the rebinning's maxima
+    P.g2_bytes = P.vmax_off + align256(rebin_max_count((long long)cv, P.n_psi, g.det_cols) * 4);
     P.gF_bytes = align256((uint64_t)nfilt * P.gf_rows * P.gf_cols * 4);
     P.gbar_bytes = align256((uint64_t)nfilt * rc * (P.det_adjoint ? 8 : 4));
     P.conv_bytes = P.det_adjoint ? align256(cv * rc * 4) : 0;
@@ -629,6 +637,16 @@ int build_plan(const katsevich_geometry &g_in, const katsevich_grid &gr,
         }
         float *hi = reinterpret_cast<float *>(img + L.hil_im);
         for (int f = 0; f < N; ++f) hi[f] = (float)P.hil_im[f];
+        // odd taps u[d] = K[2d + 1] reversed, q = Q0 - d with Q0 = 128 hil_f + 7, times 2^14
+        // (the matrix-core Hilbert's operand; zero where |2d + 1| > cols - 1)
+        float *hu = reinterpret_cast<float *>(img + L.hil_u);
+        const int nq = 256 * P.hil_f + 32, q0 = 128 * P.hil_f + 7;
+        for (int q = 0; q < nq; ++q) {
+            const int m = 2 * (q0 - q) + 1;
+            hu[q] = std::abs(m) <= cols - 1
+                        ? (float)(kHilTapScale * 2.0 * g.dalpha / (kPi * std::sin(m * g.dalpha)))
+                        : 0.0f;
+        }
     }
     {
         PiEntry *pe = reinterpret_cast<PiEntry *>(img + L.pi);
@@ -893,6 +911,7 @@ int build_plan_device(const katsevich_geometry &g_in, const katsevich_grid &gr,
     a.rows = g.det_rows;
     a.n_psi = P.n_psi;
     a.fft_len = P.fft_len;
+    a.hil_f = P.hil_f;
     a.nx = gr.nx;
     a.ny = gr.ny;
     a.nz = gr.nz;
@@ -927,6 +946,7 @@ int build_plan_device(const katsevich_geometry &g_in, const katsevich_grid &gr,
     p.cos_alpha = reinterpret_cast<float *>(tb + L.cos_alpha);
     p.twiddle = reinterpret_cast<float2 *>(tb + L.twiddle);
     p.hil_im = reinterpret_cast<float *>(tb + L.hil_im);
+    p.hil_u = reinterpret_cast<float *>(tb + L.hil_u);
     p.pi = reinterpret_cast<PiEntry *>(tb + L.pi);
     p.boxes = reinterpret_cast<BpBox *>(tb + L.boxes);
     p.tref = reinterpret_cast<TileRay *>(tb + L.tref);

@@ -43,6 +43,9 @@ constexpr int kBpBoxCols = 64;
 // would otherwise be too short to fill the GPU).
 constexpr int kFilterChunk = 512;
 constexpr uint64_t kFilterChunkBytes = 256ull << 20;
+// Scale of the matrix-core Hilbert's taps: |K[m]| <= 2/pi, so 2^14 K stays below the float16
+// maximum and the smallest taps' low halves stay normal numbers.
+constexpr double kHilTapScale = 16384.0;
 
 // Detector footprint (absolute row/col origin, may be -kPad, and extent) of one
 // backprojection tile x slice run at one pitch-relative view: every bilinear tap of
@@ -80,6 +83,7 @@ struct TableLayout {
     uint64_t cos_alpha = 0;  // float  [cols]
     uint64_t twiddle = 0;    // float2 [fft_len]  exp(-2 pi i k / N)
     uint64_t hil_im = 0;     // float  [fft_len]  Im(DFT of the Hilbert taps) / N
+    uint64_t hil_u = 0;      // float  [256 hil_f + 32]  reversed odd Hilbert taps x 2^14
     uint64_t pi = 0;         // PiEntry [n_tab][ny][nx]
     uint64_t boxes = 0;      // BpBox   [runs][tiles_y][tiles_x][W]
     uint64_t tref = 0;       // float4  [tiles_y][tiles_x][W]  the tile centre's ray (see below)
@@ -119,6 +123,8 @@ struct PlanHost {
 
     // Hilbert
     int fft_len = 0;
+    int hil_mode = 1;                      // KATS_HILBERT_FFT or KATS_HILBERT_MFMA
+    int hil_f = 1;                         // 128-column groups of one output parity (matrix cores)
     std::vector<double> hil_im;            // [fft_len], already divided by fft_len
 
     // device image
@@ -145,6 +151,7 @@ struct PlanHost {
     // or 64-bit fixed point in the deterministic mode, which also takes conv_bytes for one
     // chunk's conversion to float and det_bytes of scale scratch).
     int64_t chunk_views = 0;
+    uint64_t vmax_off = 0;                 // per-view maxima (matrix-core Hilbert) inside the g2 region
     uint64_t g4_bytes = 0, g2_bytes = 0, gF_bytes = 0, gbar_bytes = 0;
     bool det_adjoint = false;                           // KATS_FLAG_DETERMINISTIC_ADJOINT
     uint64_t conv_bytes = 0, det_bytes = 0;

@@ -172,6 +172,14 @@ __global__ __launch_bounds__(kTB) void k_plan_small(DevPlanArgs a, DevPlanPtrs p
 __global__ __launch_bounds__(kTB) void k_plan_hilbert(DevPlanArgs a, DevPlanPtrs p) {
     const int f = blockIdx.x * kTB + threadIdx.x;
     const int N = a.fft_len;
+    // the matrix-core path's operand: odd taps u[d] = K[2d + 1] reversed (q = Q0 - d,
+    // Q0 = 128 hil_f + 7) times 2^14, zero where |2d + 1| > cols - 1
+    if (f < 256 * a.hil_f + 32) {
+        const int m = 2 * (128 * a.hil_f + 7 - f) + 1;
+        p.hil_u[f] = abs(m) <= a.cols - 1
+                         ? (float)(kHilTapScale * 2.0 * a.dalpha / (kPiD * sin(m * a.dalpha)))
+                         : 0.0f;
+    }
     if (f >= N) return;
     double acc = 0.0;
     for (int m = 1; m < a.cols; m += 2) {
@@ -473,7 +481,8 @@ hipError_t launch_plan_device(const DevPlanArgs &a, const DevPlanPtrs &p, hipStr
     hipLaunchKernelGGL(k_plan_fr, dim3(blocks_for((long long)a.n_psi * a.cols)), dim3(kTB), 0, s, a, p);
     hipLaunchKernelGGL(k_plan_br, dim3(blocks_for((long long)a.rows * a.cols)), dim3(kTB), 0, s, a, p);
     hipLaunchKernelGGL(k_plan_small, dim3(blocks_for(small > a.fft_len ? small : a.fft_len)), dim3(kTB), 0, s, a, p);
-    hipLaunchKernelGGL(k_plan_hilbert, dim3(blocks_for(a.fft_len)), dim3(kTB), 0, s, a, p);
+    const int nq = 256 * a.hil_f + 32;
+    hipLaunchKernelGGL(k_plan_hilbert, dim3(blocks_for(a.fft_len > nq ? a.fft_len : nq)), dim3(kTB), 0, s, a, p);
     hipLaunchKernelGGL(k_plan_pi, dim3(blocks_for(nvox)), dim3(kTB), 0, s, a, p);
     hipLaunchKernelGGL(k_plan_pack, dim3(blocks_for(nvox)), dim3(kTB), 0, s, a, p);
     const long long cb = blocks_for(total);

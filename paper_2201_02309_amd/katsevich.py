@@ -39,7 +39,7 @@ class _Grid(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("n_psi", c_int32), ("n_threads", c_int32), ("flags", c_int32),
-                ("bp_slices", c_int32)]
+                ("bp_slices", c_int32), ("hilbert_mode", c_int32)]
 
 
 class _DevSizes(ctypes.Structure):
@@ -58,11 +58,12 @@ class _Info(ctypes.Structure):
                 ("window_views", c_int32), ("window_lo", c_int32), ("fft_len", c_int32),
                 ("commensurate", c_int32), ("gf_rows", c_int32), ("gf_cols", c_int32),
                 ("atan_degree", c_int32), ("bp_slices", c_int32), ("bp_box_rows", c_int32),
-                ("bp_box_cols", c_int32), ("half_sample", c_int32)]
+                ("bp_box_cols", c_int32), ("half_sample", c_int32), ("hilbert_mode", c_int32)]
 
 
 FLAG_HALF_SAMPLE_DERIVATIVE = 1   # KATS_FLAG_HALF_SAMPLE_DERIVATIVE (include/katsevich.h)
 FLAG_DETERMINISTIC_ADJOINT = 2    # KATS_FLAG_DETERMINISTIC_ADJOINT
+HILBERT_AUTO, HILBERT_FFT, HILBERT_MFMA = 0, 1, 2   # KATS_HILBERT_* (include/katsevich.h)
 
 # table id -> (C enum, numpy dtype, shape key)
 TABLES = {
@@ -174,14 +175,16 @@ class Plan:
     def __init__(self, geom: dict, grid: dict, n_psi: int = 0, n_threads: int = 0,
                  bind: bool = True, device=None, bp_slices: int = 0, gpu_plan: bool = False,
                  half_sample: bool = False, keep_pi_scratch: bool = False,
-                 deterministic_adjoint: bool = False):
+                 deterministic_adjoint: bool = False, hilbert_mode: int = 0):
         """gpu_plan: build the whole plan on the GPU (katsevich_plan_device) on `device` and
         its current stream, straight into the plan's table tensor (the plan is then bound
         whatever `bind` says); otherwise on the host (katsevich_plan).  keep_pi_scratch
         (gpu_plan only): keep the build's scratch, whose float64 PI tables pi_tables() reads.
         half_sample: KATS_FLAG_HALF_SAMPLE_DERIVATIVE (derivative at the centres of the
         sinogram's 2 x 2 (lambda, alpha) cells).  deterministic_adjoint:
-        KATS_FLAG_DETERMINISTIC_ADJOINT (bit-reproducible recon_backward)."""
+        KATS_FLAG_DETERMINISTIC_ADJOINT (bit-reproducible recon_backward).  hilbert_mode:
+        HILBERT_AUTO, HILBERT_FFT or HILBERT_MFMA (the Hilbert filter as register FFTs or as
+        a Toeplitz product on the matrix cores)."""
         self._lib = load_library()
         self.geom = dict(geom)
         self.grid = dict(grid)
@@ -193,7 +196,7 @@ class Plan:
         opts = _Options(n_psi=int(n_psi), n_threads=int(n_threads),
                         flags=(FLAG_HALF_SAMPLE_DERIVATIVE if half_sample else 0) |
                         (FLAG_DETERMINISTIC_ADJOINT if deterministic_adjoint else 0),
-                        bp_slices=int(bp_slices))
+                        bp_slices=int(bp_slices), hilbert_mode=int(hilbert_mode))
         g, gr = _geom_struct(geom), _grid_struct(grid)
         if gpu_plan:
             import torch

@@ -75,6 +75,23 @@ def test_rejects_unknown_flags():
     assert st == -2 and b"flags" in lib.katsevich_last_error()
 
 
+def test_hilbert_mode_option():
+    """hilbert_mode: auto and 1 run the FFT, 2 the matrix-core product (the plan reports the
+    path); other values are rejected."""
+    wl = configs.tiny()
+    g, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    assert pk.Plan(g, gr, bind=False).info["hilbert_mode"] == pk.katsevich.HILBERT_FFT
+    assert pk.Plan(g, gr, bind=False, hilbert_mode=1).info["hilbert_mode"] == pk.katsevich.HILBERT_FFT
+    p2 = pk.Plan(g, gr, bind=False, hilbert_mode=2)
+    assert p2.info["hilbert_mode"] == pk.katsevich.HILBERT_MFMA
+    # the matrix-core path's per-group maxima live in the workspace
+    assert p2.info["workspace_bytes"] >= pk.Plan(g, gr, bind=False).info["workspace_bytes"]
+    for bad in (-1, 3):
+        with pytest.raises(pk.KatsevichError) as e:
+            pk.Plan(g, gr, bind=False, hilbert_mode=bad)
+        assert e.value.status == -2 and "hilbert_mode" in str(e.value)
+
+
 def test_rejects_invalid_grid():
     wl = configs.config1()
     gr = wl.grid.as_dict()
