@@ -90,12 +90,12 @@ typedef struct katsevich_options {
 } katsevich_options;
 
 /* hilbert_mode: how the Hilbert filter (eq. HF) of katsevich_filter / katsevich_recon runs.
- * KATS_HILBERT_AUTO (0) picks KATS_HILBERT_FFT; KATS_HILBERT_FFT (1): zero-padded linear
+ * KATS_HILBERT_AUTO (0) picks KATS_HILBERT_MFMA; KATS_HILBERT_FFT (1): zero-padded linear
  * convolution by register FFTs (float32); KATS_HILBERT_MFMA (2): the same convolution as a
  * dense Toeplitz product on the matrix cores (even and odd output columns from the odd and
  * even inputs, float32 operands split into float16 pairs with power-of-two range scaling per
- * group of kappa rows, float32 accumulation; agrees with the FFT to ~2.5e-7 relative, and
- * costs a forward-rebinning pass of its own).  The adjoint (katsevich_recon_backward) always
+ * group of kappa rows, float32 accumulation, the forward rebinning as a pass of its own;
+ * agrees with the FFT to ~2.5e-7 relative).  The adjoint (katsevich_recon_backward) always
  * uses the FFT.  Other values: KATS_EINVAL_GEOMETRY. */
 #define KATS_HILBERT_AUTO 0
 #define KATS_HILBERT_FFT 1

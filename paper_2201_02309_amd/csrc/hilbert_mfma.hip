@@ -12,8 +12,8 @@
 // Precision.  Float32 operands are split into float16 pairs, v = hi + lo with
 // hi = fp16(v), lo = fp16(v - hi) (22 significant bits), and each product is
 // hi_x hi_u + hi_x lo_u + lo_x hi_u with float32 accumulation (the dropped lo_x lo_u is 2^-22
-// of the product).  Ranges: each group of a view's kappa rows is scaled by a power of two
-// 2^-E with max |x| < 2^E over the group, so |x 2^-E| < 1; the taps come from the plan
+// of the product).  Ranges: each group of kappa rows (16 lines of 4 views) is scaled by a
+// power of two 2^-E with max |x| < 2^E over the group, so |x 2^-E| < 1; the taps come from the plan
 // scaled by 2^14 (|K| <= 2/pi, so no float16 overflow and the smallest taps keep normal low
 // halves).  The outputs are scaled
 // back by exact powers of two.
@@ -21,8 +21,9 @@
 // Layout.  A workgroup of 8 waves takes tiles of 64 kappa rows (persistent over the chunk's
 // tiles).  Waves 0-3 form the even outputs (A = x_o), waves 4-7 the odd ones (A = x_e); each
 // wave owns a quarter of the NP = 128 F padded outputs, F fragments of 32 columns, for both
-// 32-row halves of the tile: 2 F 32 x 32 float32 accumulators.  K runs in chunks of 32
-// (two v_mfma_f32_32x32x16_f16 steps) through double-buffered LDS tiles of the split rows.
+// 32-row halves of the tile: 2 F 32 x 32 float32 accumulators.  K runs in chunks of 64
+// (four v_mfma_f32_32x32x16_f16 steps) through double-buffered LDS tiles of the split rows
+// (chunks of 32 measured 0.04 ms slower over the clinical filter: twice the barriers).
 // The B fragments are read from the reversed tap sequence in LDS: a lane's 8 consecutive K
 // entries of one column are 8 consecutive reversed taps, and 8 copies of that sequence
 // shifted by 0..7 make every such read one aligned 16-byte load.
@@ -36,12 +37,13 @@ namespace {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half4v __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kMT = 64;          // kappa rows per tile
+constexpr int kMT = kHilTileRows; // kappa rows per tile
 constexpr int kHT = 512;         // threads per workgroup (8 waves)
-constexpr int kKC = 32;          // K chunk (two 16-deep MFMA steps)
-constexpr int kAP = 40;          // LDS row pitch of the A tiles in halves: 80 bytes, so the
+constexpr int kKC = 64;          // K chunk (four 16-deep MFMA steps)
+constexpr int kAP = 72;          // LDS row pitch of the A tiles in halves: 144 bytes, so the
                                  // 16-byte fragment reads of 8 consecutive rows cover all banks
 
 template <int F>
@@ -67,8 +69,8 @@ __device__ inline int scale_exponent(unsigned bits) {
     return e < -125 ? -125 : (e > 127 ? 127 : e);
 }
 
-// In place on the rebinned kappa rows g4 [rows of the chunk][cols]; rmax: max |g3| per (view,
-// group of kRebinLines lines, block of kDRThreads columns).  A tile's rows are read completely (through LDS) before any
+// In place on the rebinned kappa rows g4 [rows of the chunk][cols]; rmax: max |g3| per (4
+// views, group of kRebinLines lines, block of kDRThreads columns).  A tile's rows are read completely (through LDS) before any
 // of them is written.
 template <int F>
 __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restrict__ g4,
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
         S.u[1][s][q] = (_Float16)(v - (float)h);
     }
 
-    // staging role: 4 consecutive columns (two of each parity) of rows rg and rg + 32
+    // staging role: 8 consecutive columns (four of each parity) of rows rg and rg + 32
     const int sq = tid & 15, rg = tid >> 4;
     const bool vec = (cols & 3) == 0;             // rows 16-byte aligned: float4 loads
     // compute role
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
             float is = 0.0f, os = 0.0f;
             if (R < nrows) {
                 const long long i = R / p.n_psi;
-                const long long grp = i * ngr + (R - i * p.n_psi) / kRebinLines;
+                const long long grp = (i / kRebinViews) * ngr + (R - i * p.n_psi) / kRebinLines;
                 float m = 0.0f;
                 for (int j = 0; j < nvb; ++j) m = fmaxf(m, rmax[grp * nvb + j]);
                 const int E = scale_exponent(__float_as_uint(m));
@@ -133,41 +135,45 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
 
         // staging, pipelined over the K chunks: chunk ch + 1 is loaded before chunk ch's
         // products and scaled, split and stored into the other LDS buffer after them
-        float x[2][4];
+        float x[2][8];
         auto load = [&](int ch) {
-            const int c0 = ch * 2 * kKC + 4 * sq;
+            const int c0 = ch * 2 * kKC + 8 * sq;
 #pragma unroll
             for (int rr = 0; rr < 2; ++rr) {
-                if (vec && rok[rr] && c0 + 3 < cols) {
-                    const float4 v = *reinterpret_cast<const float4 *>(srow[rr] + c0);
-                    x[rr][0] = v.x; x[rr][1] = v.y; x[rr][2] = v.z; x[rr][3] = v.w;
-                } else {
 #pragma unroll
-                    for (int cc = 0; cc < 4; ++cc)
-                        x[rr][cc] = (rok[rr] && c0 + cc < cols) ? srow[rr][c0 + cc] : 0.0f;
+                for (int h = 0; h < 2; ++h) {
+                    const int c1 = c0 + 4 * h;
+                    if (vec && rok[rr] && c1 + 3 < cols) {
+                        const float4 v = *reinterpret_cast<const float4 *>(srow[rr] + c1);
+                        x[rr][4 * h + 0] = v.x; x[rr][4 * h + 1] = v.y; x[rr][4 * h + 2] = v.z; x[rr][4 * h + 3] = v.w;
+                    } else {
+#pragma unroll
+                        for (int cc = 0; cc < 4; ++cc)
+                            x[rr][4 * h + cc] = (rok[rr] && c1 + cc < cols) ? srow[rr][c1 + cc] : 0.0f;
+                    }
                 }
             }
         };
         auto store = [&](int b) {
 #pragma unroll
             for (int rr = 0; rr < 2; ++rr) {
-                float v[4];
+                float v[8];
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) v[cc] = x[rr][cc] * isc[rr];
-                half2v hi_e, lo_e, hi_o, lo_o;
+                for (int cc = 0; cc < 8; ++cc) v[cc] = x[rr][cc] * isc[rr];
+                half4v hi_e, lo_e, hi_o, lo_o;
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < 4; ++j) {
                     const _Float16 he = (_Float16)v[2 * j], ho = (_Float16)v[2 * j + 1];
                     hi_e[j] = he;
                     lo_e[j] = (_Float16)(v[2 * j] - (float)he);
                     hi_o[j] = ho;
                     lo_o[j] = (_Float16)(v[2 * j + 1] - (float)ho);
                 }
-                const int o = (rg + 32 * rr) * kAP + 2 * sq;
-                *reinterpret_cast<half2v *>(&S.a[b][0][o]) = hi_e;
-                *reinterpret_cast<half2v *>(&S.a[b][1][o]) = lo_e;
-                *reinterpret_cast<half2v *>(&S.a[b][2][o]) = hi_o;
-                *reinterpret_cast<half2v *>(&S.a[b][3][o]) = lo_o;
+                const int o = (rg + 32 * rr) * kAP + 4 * sq;
+                *reinterpret_cast<half4v *>(&S.a[b][0][o]) = hi_e;
+                *reinterpret_cast<half4v *>(&S.a[b][1][o]) = lo_e;
+                *reinterpret_cast<half4v *>(&S.a[b][2][o]) = hi_o;
+                *reinterpret_cast<half4v *>(&S.a[b][3][o]) = lo_o;
             }
         };
 
@@ -216,11 +222,14 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
             if (more) load(ch + 1);
             kstep(b, ch, 0);
             kstep(b, ch, 1);
+            kstep(b, ch, 2);
+            kstep(b, ch, 3);
             if (more) store(b ^ 1);
             __syncthreads();
         }
 
         // accumulator element i of a lane: row 8 (i / 4) + 4 (lane / 32) + i % 4, column lane % 32
+        // (staging the results through LDS for 16-byte stores measured no faster)
 #pragma unroll
         for (int mf = 0; mf < 2; ++mf)
 #pragma unroll
@@ -242,7 +251,7 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
 hipError_t launch_hilbert_mfma(const KParams &k, float *g4, const float *rmax, hipStream_t s) {
     const long long ntiles = (k.n_filt * (long long)k.n_psi + kMT - 1) / kMT;
     if (ntiles <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)(ntiles < 256 ? ntiles : 256);
+    const unsigned blocks = (unsigned)(ntiles < kHilBlocks ? ntiles : kHilBlocks);
     switch (k.hil_f) {
         case 1: hipLaunchKernelGGL(k_hilbert_mfma<1>, dim3(blocks), dim3(kHT), 0, s, k, g4, rmax); break;
         case 2: hipLaunchKernelGGL(k_hilbert_mfma<2>, dim3(blocks), dim3(kHT), 0, s, k, g4, rmax); break;

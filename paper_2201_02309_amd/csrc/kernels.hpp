@@ -74,12 +74,14 @@ hipError_t launch_hilbert_mfma(const KParams &k, float *g4, const float *vmax, h
 // Forward filter chain on views first_view..last_view:
 //   g2 = deriv+LW(sino); g4 = Hilbert(FR(g2)); gF = cos * BR(g4).
 // Matrix-core Hilbert path: the forward rebinning runs as a kernel of its own (one thread per
-// (view, column, group of kRebinLines kappa lines)) and leaves one max |g3| per (view, line
-// group, block of kDRThreads columns) for the Hilbert's range scaling.
+// (4 views, column, group of kRebinLines kappa lines)) and leaves one max |g3| per (4 views,
+// line group, block of kDRThreads columns) for the Hilbert's range scaling.
 constexpr int kDRThreads = 128;
 constexpr int kRebinLines = 16;
+constexpr int kRebinViews = 4;
 inline uint64_t rebin_max_count(long long n_filt, int n_psi, int cols) {
-    return (uint64_t)n_filt * ((n_psi + kRebinLines - 1) / kRebinLines) * ((cols + kDRThreads - 1) / kDRThreads);
+    return (uint64_t)((n_filt + kRebinViews - 1) / kRebinViews) * ((n_psi + kRebinLines - 1) / kRebinLines) *
+           ((cols + kDRThreads - 1) / kDRThreads);
 }
 // vmax: those maxima (MFMA path only).
 hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,

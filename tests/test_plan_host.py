@@ -76,16 +76,16 @@ def test_rejects_unknown_flags():
 
 
 def test_hilbert_mode_option():
-    """hilbert_mode: auto and 1 run the FFT, 2 the matrix-core product (the plan reports the
+    """hilbert_mode: auto and 2 run the matrix-core product, 1 the FFT (the plan reports the
     path); other values are rejected."""
     wl = configs.tiny()
     g, gr = wl.geom.as_dict(), wl.grid.as_dict()
-    assert pk.Plan(g, gr, bind=False).info["hilbert_mode"] == pk.katsevich.HILBERT_FFT
-    assert pk.Plan(g, gr, bind=False, hilbert_mode=1).info["hilbert_mode"] == pk.katsevich.HILBERT_FFT
-    p2 = pk.Plan(g, gr, bind=False, hilbert_mode=2)
-    assert p2.info["hilbert_mode"] == pk.katsevich.HILBERT_MFMA
+    assert pk.Plan(g, gr, bind=False).info["hilbert_mode"] == pk.katsevich.HILBERT_MFMA
+    assert pk.Plan(g, gr, bind=False, hilbert_mode=2).info["hilbert_mode"] == pk.katsevich.HILBERT_MFMA
+    p1 = pk.Plan(g, gr, bind=False, hilbert_mode=1)
+    assert p1.info["hilbert_mode"] == pk.katsevich.HILBERT_FFT
     # the matrix-core path's per-group maxima live in the workspace
-    assert p2.info["workspace_bytes"] >= pk.Plan(g, gr, bind=False).info["workspace_bytes"]
+    assert pk.Plan(g, gr, bind=False).info["workspace_bytes"] >= p1.info["workspace_bytes"]
     for bad in (-1, 3):
         with pytest.raises(pk.KatsevichError) as e:
             pk.Plan(g, gr, bind=False, hilbert_mode=bad)
