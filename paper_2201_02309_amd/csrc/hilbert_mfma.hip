@@ -13,17 +13,18 @@
 // hi = fp16(v), lo = fp16(v - hi) (22 significant bits), and each product is
 // hi_x hi_u + hi_x lo_u + lo_x hi_u with float32 accumulation (the dropped lo_x lo_u is 2^-22
 // of the product).  Ranges: each group of kappa rows (16 lines of 4 views) is scaled by a
-// power of two 2^-E with max |x| < 2^E over the group, so |x 2^-E| < 1; the taps come from the plan
-// scaled by 2^14 (|K| <= 2/pi, so no float16 overflow and the smallest taps keep normal low
-// halves).  The outputs are scaled
-// back by exact powers of two.
+// power of two 2^-E with max |x| < 2^E over the group, so |x 2^-E| < 1; the taps come from
+// the plan scaled by 2^14 (|K| <= 2/pi, so no float16 overflow and the smallest taps keep
+// normal low halves).  The outputs are scaled back by exact powers of two.
 //
-// Layout.  A workgroup of 8 waves takes tiles of 64 kappa rows (persistent over the chunk's
-// tiles).  Waves 0-3 form the even outputs (A = x_o), waves 4-7 the odd ones (A = x_e); each
-// wave owns a quarter of the NP = 128 F padded outputs, F fragments of 32 columns, for both
-// 32-row halves of the tile: 2 F 32 x 32 float32 accumulators.  K runs in chunks of 64
-// (four v_mfma_f32_32x32x16_f16 steps) through double-buffered LDS tiles of the split rows
-// (chunks of 32 measured 0.04 ms slower over the clinical filter: twice the barriers).
+// Layout.  A workgroup of 8 waves takes tiles of kMT = 32 kappa rows (persistent over the
+// chunk's tiles, two workgroups per CU).  Waves 0-3 form the even outputs (A = x_o), waves 4-7
+// the odd ones (A = x_e); each wave owns a quarter of the NP = 128 F padded outputs, F
+// fragments of 32 columns of the tile's rows: F 32 x 32 float32 accumulators.  K runs in
+// chunks of 64 (four v_mfma_f32_32x32x16_f16 steps) through double-buffered LDS tiles of the
+// split rows.  Measured on the clinical filter: chunks of 32 were 0.04 ms slower (twice the
+// barriers); tiles of 64 rows (two 32-row fragments per wave, B fragments read once for
+// both, but 254 VGPRs and one workgroup per CU) 0.06 ms slower.
 // The B fragments are read from the reversed tap sequence in LDS: a lane's 8 consecutive K
 // entries of one column are 8 consecutive reversed taps, and 8 copies of that sequence
 // shifted by 0..7 make every such read one aligned 16-byte load.
@@ -41,6 +42,8 @@ typedef _Float16 half4v __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMT = kHilTileRows; // kappa rows per tile
+constexpr int kMF = kMT / 32;     // 32-row fragments per wave
+constexpr int kRPT = kMT / 32;    // staging rows per thread (16 threads per row)
 constexpr int kHT = 512;         // threads per workgroup (8 waves)
 constexpr int kKC = 64;          // K chunk (four 16-deep MFMA steps)
 constexpr int kAP = 72;          // LDS row pitch of the A tiles in halves: 144 bytes, so the
@@ -70,10 +73,10 @@ __device__ inline int scale_exponent(unsigned bits) {
 }
 
 // In place on the rebinned kappa rows g4 [rows of the chunk][cols]; rmax: max |g3| per (4
-// views, group of kRebinLines lines, block of kDRThreads columns).  A tile's rows are read completely (through LDS) before any
-// of them is written.
+// views, group of kRebinLines lines, block of kDRThreads columns).  A tile's rows are read
+// completely (through LDS) before any of them is written.
 template <int F>
-__global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restrict__ g4,
+__global__ __launch_bounds__(kHT, 4) void k_hilbert_mfma(KParams p, float *__restrict__ g4,
                                                       const float *__restrict__ rmax) {
     using H = HilShape<F>;
     __shared__ HilShared<F> S;
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
         S.u[1][s][q] = (_Float16)(v - (float)h);
     }
 
-    // staging role: 8 consecutive columns (four of each parity) of rows rg and rg + 32
+    // staging role: 8 consecutive columns (four of each parity) of rows rg + 32 rr, rr < kRPT
     const int sq = tid & 15, rg = tid >> 4;
     const bool vec = (cols & 3) == 0;             // rows 16-byte aligned: float4 loads
     // compute role
@@ -122,24 +125,26 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
             S.iscale[tid] = is;
             S.oscale[tid] = os;
         }
-        const float *srow[2];
-        bool rok[2];
+        const float *srow[kRPT];
+        bool rok[kRPT];
 #pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
+        for (int rr = 0; rr < kRPT; ++rr) {
             const long long R = R0 + rg + 32 * rr;
             rok[rr] = R < nrows;
             srow[rr] = g4 + (rok[rr] ? R : 0) * cols;
         }
         __syncthreads();
-        const float isc[2] = {S.iscale[rg], S.iscale[rg + 32]};
+        float isc[kRPT];
+#pragma unroll
+        for (int rr = 0; rr < kRPT; ++rr) isc[rr] = S.iscale[rg + 32 * rr];
 
         // staging, pipelined over the K chunks: chunk ch + 1 is loaded before chunk ch's
         // products and scaled, split and stored into the other LDS buffer after them
-        float x[2][8];
+        float x[kRPT][8];
         auto load = [&](int ch) {
             const int c0 = ch * 2 * kKC + 8 * sq;
 #pragma unroll
-            for (int rr = 0; rr < 2; ++rr) {
+            for (int rr = 0; rr < kRPT; ++rr) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int c1 = c0 + 4 * h;
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
         };
         auto store = [&](int b) {
 #pragma unroll
-            for (int rr = 0; rr < 2; ++rr) {
+            for (int rr = 0; rr < kRPT; ++rr) {
                 float v[8];
 #pragma unroll
                 for (int cc = 0; cc < 8; ++cc) v[cc] = x[rr][cc] * isc[rr];
@@ -177,18 +182,18 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
             }
         };
 
-        f32x16 acc[2][F];
+        f32x16 acc[kMF][F];
 #pragma unroll
-        for (int mf = 0; mf < 2; ++mf)
+        for (int mf = 0; mf < kMF; ++mf)
 #pragma unroll
             for (int nf = 0; nf < F; ++nf) acc[mf][nf] = (f32x16){};
 
         // one 16-deep K step from buffer b
         auto kstep = [&](int b, int ch, int ks) {
             const int kl = ks * 16 + kl0;
-            half8 ah[2], al[2];
+            half8 ah[kMF], al[kMF];
 #pragma unroll
-            for (int mf = 0; mf < 2; ++mf) {
+            for (int mf = 0; mf < kMF; ++mf) {
                 const int o = (mf * 32 + nl) * kAP + kl;
                 ah[mf] = *reinterpret_cast<const half8 *>(&S.a[b][ab][o]);
                 al[mf] = *reinterpret_cast<const half8 *>(&S.a[b][ab + 1][o]);
@@ -201,13 +206,13 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
                 const half8 bh = *reinterpret_cast<const half8 *>(&S.u[0][s][qq]);
                 const half8 bl = *reinterpret_cast<const half8 *>(&S.u[1][s][qq]);
 #pragma unroll
-                for (int mf = 0; mf < 2; ++mf)
+                for (int mf = 0; mf < kMF; ++mf)
                     acc[mf][nf] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[mf], bh, acc[mf][nf], 0, 0, 0);
 #pragma unroll
-                for (int mf = 0; mf < 2; ++mf)
+                for (int mf = 0; mf < kMF; ++mf)
                     acc[mf][nf] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[mf], bl, acc[mf][nf], 0, 0, 0);
 #pragma unroll
-                for (int mf = 0; mf < 2; ++mf)
+                for (int mf = 0; mf < kMF; ++mf)
                     acc[mf][nf] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[mf], bh, acc[mf][nf], 0, 0, 0);
             }
         };
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(kHT) void k_hilbert_mfma(KParams p, float *__restri
         // accumulator element i of a lane: row 8 (i / 4) + 4 (lane / 32) + i % 4, column lane % 32
         // (staging the results through LDS for 16-byte stores measured no faster)
 #pragma unroll
-        for (int mf = 0; mf < 2; ++mf)
+        for (int mf = 0; mf < kMF; ++mf)
 #pragma unroll
             for (int nf = 0; nf < F; ++nf) {
                 const int c = 2 * ((quarter * F + nf) * 32 + nl) + par;

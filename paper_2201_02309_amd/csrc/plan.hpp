@@ -46,11 +46,11 @@ constexpr uint64_t kFilterChunkBytes = 256ull << 20;
 // Scale of the matrix-core Hilbert's taps: |K[m]| <= 2/pi, so 2^14 K stays below the float16
 // maximum and the smallest taps' low halves stay normal numbers.
 constexpr double kHilTapScale = 16384.0;
-// Matrix-core Hilbert: kappa rows per tile and persistent workgroups (one per CU of the
+// Matrix-core Hilbert: kappa rows per tile and persistent workgroups (two per CU of the
 // MI355X), so one round of tiles holds kHilTileRows x kHilBlocks rows; its chunks of views are
 // cut to whole rounds (a chunk of 512 clinical views is 4.03 rounds: the 0.03 takes a fifth).
-constexpr int kHilTileRows = 64;
-constexpr int kHilBlocks = 256;
+constexpr int kHilTileRows = 32;
+constexpr int kHilBlocks = 512;
 
 // Detector footprint (absolute row/col origin, may be -kPad, and extent) of one
 // backprojection tile x slice run at one pitch-relative view: every bilinear tap of
