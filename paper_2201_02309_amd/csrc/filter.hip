@@ -19,10 +19,13 @@ constexpr int kFftThreads = 256;
 
 constexpr int kDerivRun = 16;     // filtered views per thread in k_deriv_lw
 constexpr int kBrBlocks = 8;      // row blocks of a view in k_br_cos
+constexpr int kBrUnroll = 12;     // rows per thread with every load issued first
 
-// One thread per (detector row, column) walks a run of consecutive views, so each
-// sinogram sample comes from HBM once: the previous / current / next views stay in
-// registers and the neighbouring columns of the current view hit the cache.
+// One thread per (detector row, column) takes a run of consecutive views, so each sinogram
+// sample comes from HBM about once: the run's samples (plus one view on each side) are loaded
+// into registers, every load issued before the first use (0.03 ms faster over the clinical
+// filter than a walk keeping the previous / current / next views), and the neighbouring
+// columns of each view hit the cache.
 __global__ __launch_bounds__(kElemThreads) void k_deriv_lw(KParams p, const float *__restrict__ sino,
                                                            float *__restrict__ g2) {
     const int c = blockIdx.x * kElemThreads + threadIdx.x;
@@ -34,25 +37,28 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_lw(KParams p, const floa
     const float *col = sino + (size_t)r * p.cols + c;         // sample (view 0, r, c)
     const float w = p.lw[r];
     long long n = p.first_view + i0;                           // 1 <= n <= n_views-2
-    float prev = col[(size_t)(n - 1) * rc];
-    float cur = col[(size_t)n * rc];
-    for (long long i = i0; i < i1; ++i, ++n) {
-        const float next = col[(size_t)(n + 1) * rc];
-        const float *g0 = col + (size_t)n * rc;
-        const float left = c > 0 ? g0[-1] : 0.0f;
-        const float right = c + 1 < p.cols ? g0[1] : 0.0f;
-        const float dl = (next - prev) * p.inv_2dlam;
-        const float da = (right - left) * p.inv_2dalpha;
-        g2[(size_t)i * rc + (size_t)r * p.cols + c] = w * (dl + da);
-        prev = cur;
-        cur = next;
+    // all of the run's loads issued before the first use
+    float x[kDerivRun + 2], lf[kDerivRun], rt[kDerivRun];
+    const int nr = (int)(i1 - i0);
+#pragma unroll
+    for (int j = 0; j < kDerivRun + 2; ++j) x[j] = j < nr + 2 ? col[(size_t)(n - 1 + j) * rc] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < kDerivRun; ++j) {
+        const float *g0 = col + (size_t)(n + j) * rc;
+        lf[j] = (j < nr && c > 0) ? g0[-1] : 0.0f;
+        rt[j] = (j < nr && c + 1 < p.cols) ? g0[1] : 0.0f;
     }
+#pragma unroll
+    for (int j = 0; j < kDerivRun; ++j)
+        if (j < nr)
+            g2[(size_t)(i0 + j) * rc + (size_t)r * p.cols + c] =
+                w * ((x[j + 2] - x[j]) * p.inv_2dlam + (rt[j] - lf[j]) * p.inv_2dalpha);
 }
 
 // Half-sample derivative: filtered view i (cell-centre view n = first_view + i, between
 // sinogram views n and n+1) and column c (between sinogram columns c and c+1).  Each partial
 // derivative is the mean of the two forward differences across the 2 x 2 cell; the thread
-// walks a run of views keeping the previous sinogram view's two samples in registers.
+// loads the two columns of its run of views (plus the next view) before the first use.
 __global__ __launch_bounds__(kElemThreads) void k_deriv_lw_half(KParams p, const float *__restrict__ sino,
                                                                 float *__restrict__ g2) {
     const int c = blockIdx.x * kElemThreads + threadIdx.x;
@@ -65,14 +71,21 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_lw_half(KParams p, const
     const float *col = sino + (size_t)r * p.sino_cols + c;    // sinogram (view 0, r, c)
     const float w = p.lw[r];
     long long n = p.first_view + i0;                          // 0 <= n, n+1 <= sino_views-1
-    float a0 = col[(size_t)n * src], a1 = col[(size_t)n * src + 1];
-    for (long long i = i0; i < i1; ++i, ++n) {
-        const float b0 = col[(size_t)(n + 1) * src], b1 = col[(size_t)(n + 1) * src + 1];
-        const float dl = ((b0 - a0) + (b1 - a1)) * p.inv_2dlam;
-        const float da = ((a1 - a0) + (b1 - b0)) * p.inv_2dalpha;
-        g2[(size_t)i * rc + (size_t)r * p.cols + c] = w * (dl + da);
-        a0 = b0;
-        a1 = b1;
+    // all of the run's loads issued before the first use
+    float x0[kDerivRun + 1], x1[kDerivRun + 1];
+    const int nr = (int)(i1 - i0);
+#pragma unroll
+    for (int j = 0; j < kDerivRun + 1; ++j) {
+        x0[j] = j < nr + 1 ? col[(size_t)(n + j) * src] : 0.0f;
+        x1[j] = j < nr + 1 ? col[(size_t)(n + j) * src + 1] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < kDerivRun; ++j) {
+        if (j < nr) {
+            const float dl = ((x0[j + 1] - x0[j]) + (x1[j + 1] - x1[j])) * p.inv_2dlam;
+            const float da = ((x1[j] - x0[j]) + (x1[j + 1] - x0[j + 1])) * p.inv_2dalpha;
+            g2[(size_t)(i0 + j) * rc + (size_t)r * p.cols + c] = w * (dl + da);
+        }
     }
 }
 
@@ -416,11 +429,12 @@ __global__ __launch_bounds__(kDRThreads) void k_rebin(KParams p, const float *__
 }
 
 // Writes the zero-padded view [gf_rows][gf_cols] (border = 0).  One thread per (view,
-// padded column, block of rows) walks its rows: successive rows use neighbouring
+// padded column, block of rows) takes its rows: successive rows use neighbouring
 // kappa-lines of the same column (psi_hat rises with w), which the cache keeps, so g4 is
 // read about once.  Views run along x (no 65535 limit), row blocks along z: eight blocks
 // of a view's rows keep more short walks in flight than one walk over every row (clinical
-// filter 2.32 -> 2.23 ms with the shorter derivative runs).
+// filter 2.32 -> 2.23 ms with the shorter derivative runs), and a block of up to kBrUnroll
+// rows issues all its table and tap loads before the first use (1.87 -> 1.79 ms).
 __global__ __launch_bounds__(kElemThreads) void k_br_cos(KParams p, const float *__restrict__ g4,
                                                          float *__restrict__ gF) {
     const long long i = blockIdx.x;
@@ -434,6 +448,30 @@ __global__ __launch_bounds__(kElemThreads) void k_br_cos(KParams p, const float 
     float *out = gF + (size_t)i * p.gf_rows * pitch + cp;
     const float *v4 = g4 + (size_t)i * p.n_psi * p.cols + c;
     const float ca = incol ? p.cos_alpha[c] : 0.0f;
+    if (rp1 - rp0 <= kBrUnroll) {
+        // all table entries, then all taps, in flight before the first use
+        int kk[kBrUnroll];
+        float tt[kBrUnroll], xa[kBrUnroll], xb[kBrUnroll];
+#pragma unroll
+        for (int j = 0; j < kBrUnroll; ++j) {
+            const int r = rp0 + j - kPad;
+            kk[j] = -1;
+            tt[j] = 0.0f;
+            if (rp0 + j < rp1 && incol && (unsigned)r < (unsigned)p.rows) {
+                kk[j] = p.br_k[r * p.cols + c];
+                tt[j] = p.br_w[r * p.cols + c];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kBrUnroll; ++j) {
+            xa[j] = kk[j] >= 0 ? v4[kk[j] * p.cols] : 0.0f;
+            xb[j] = kk[j] >= 0 ? v4[(kk[j] + 1) * p.cols] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < kBrUnroll; ++j)
+            if (rp0 + j < rp1) out[(size_t)(rp0 + j) * pitch] = ca * ((1.0f - tt[j]) * xa[j] + tt[j] * xb[j]);
+        return;
+    }
     for (int rp = rp0; rp < rp1; ++rp) {
         const int r = rp - kPad;
         float o = 0.0f;
