@@ -29,6 +29,14 @@ CASES = {
     "odd-47-columns": (lambda: configs.tiny(nxy=16, nz=8, cols=47, rows=8, views_per_turn=72,
                                             turns=4, feed=24.0, dxy=2.0), {}),
     "parity-64^3 half-sample": (configs.config1, {"half_sample": True}),
+    # the other product widths: 2 fragments per wave (257-512 columns), 4 (769-1024), the
+    # largest detector a plan accepts and a ragged width beside it
+    "wide-300-columns": (lambda: configs.tiny(nxy=16, nz=8, cols=300, rows=8, views_per_turn=72,
+                                              turns=4, feed=24.0, dxy=2.0), {}),
+    "wide-1023-columns": (lambda: configs.tiny(nxy=16, nz=8, cols=1023, rows=8, views_per_turn=72,
+                                               turns=4, feed=24.0, dxy=2.0), {}),
+    "max-1024-columns": (lambda: configs.tiny(nxy=16, nz=8, cols=1024, rows=8, views_per_turn=72,
+                                              turns=4, feed=24.0, dxy=2.0), {}),
 }
 
 
