@@ -1,5 +1,8 @@
 // Adjoint of the backprojection (the transpose of the operator in bp.hip), for the
 // gradient of a reconstruction loss with respect to the filtered data.
+#include <algorithm>
+#include <cmath>
+
 #include "bp_common.hpp"
 
 namespace kats {
@@ -64,7 +67,9 @@ __device__ inline unsigned long long to_fixed(float v, double S) {
 //     alpha* - alpha_c = atan2(du v_c - u_c dv, rho_c^2 + u_c du + v_c dv),
 // an angle of a few cells whose float32 error is ~1e-6 cell, and atan of its small tangent
 // is the odd series through t^11 (remainder below t^13/13: ~1e-17 at the tangents of
-// voxels in the field of view).
+// voxels in the field of view).  Geometries whose tiles subtend wide angles from the source
+// (helix radius not large against the tile; see series_serves) take atan2f of the same two
+// terms instead.
 //
 // DET (deterministic mode): the boxes accumulate 64-bit integers, each contribution v
 // entering as round(v S) (the split between the two columns taken in integers, so that
@@ -76,7 +81,7 @@ template <int KZ, bool FB, bool DET>
 __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, void *__restrict__ gFout,
                          const double *__restrict__ fscale, int rows, int cols, long long first_view,
                          const float4 *__restrict__ view_tab, const uint2 *__restrict__ box_tab,
-                         const float4 *__restrict__ ray_tab, int bxi, int byi, int bz,
+                         const float4 *__restrict__ ray_tab, int series, int bxi, int byi, int bz,
                          BpTShared<KZ, DET> &S) {
     using Acc = typename BpTShared<KZ, DET>::Acc;
     typedef __attribute__((address_space(3))) Acc LdsAcc;
@@ -208,14 +213,20 @@ __device__ void bpT_tile(const BpArgs p, const float *__restrict__ fvol, void *_
         const float rinv = __builtin_amdgcn_rsqf(fmaf(u, u, v * v));
         const float tn = fmaf(du, ray.z, -ray.y * dv);
         const float td = fmaf(ray.y, du, fmaf(ray.z, dv, ray.w));
-        const float t = tn * __builtin_amdgcn_rcpf(td);
-        const float s2 = t * t;
-        float qa = fmaf(s2, -1.0f / 11.0f, 1.0f / 9.0f);
-        qa = fmaf(qa, s2, -1.0f / 7.0f);
-        qa = fmaf(qa, s2, 1.0f / 5.0f);
-        qa = fmaf(qa, s2, -1.0f / 3.0f);
-        qa = fmaf(qa, s2, 1.0f);
-        const float cc = med3(fmaf(t * qa, p.inv_dalpha, ray.x), 0.0f, (float)(b.nc - 2));
+        float dang;                                 // alpha* - alpha_c
+        if (series) {
+            const float t = tn * __builtin_amdgcn_rcpf(td);
+            const float s2 = t * t;
+            float qa = fmaf(s2, -1.0f / 11.0f, 1.0f / 9.0f);
+            qa = fmaf(qa, s2, -1.0f / 7.0f);
+            qa = fmaf(qa, s2, 1.0f / 5.0f);
+            qa = fmaf(qa, s2, -1.0f / 3.0f);
+            qa = fmaf(qa, s2, 1.0f);
+            dang = t * qa;
+        } else {
+            dang = atan2f(tn, td);
+        }
+        const float cc = med3(fmaf(dang, p.inv_dalpha, ray.x), 0.0f, (float)(b.nc - 2));
         const int c0 = (int)cc;
         const float tc = cc - (float)c0;
         const float q = p.q_scale * rinv;
@@ -312,23 +323,41 @@ __global__ __launch_bounds__(kNT) void k_bpT_lds(BpArgs p, const float *__restri
                                                  int cols, long long first_view,
                                                  const float4 *__restrict__ view_tab,
                                                  const uint2 *__restrict__ box_tab,
-                                                 const float4 *__restrict__ ray_tab) {
+                                                 const float4 *__restrict__ ray_tab, int series) {
     __shared__ BpTShared<KZ, DET> S;
-    bpT_tile<KZ, FB, DET>(p, fvol, gFout, fscale, rows, cols, first_view, view_tab, box_tab, ray_tab,
+    bpT_tile<KZ, FB, DET>(p, fvol, gFout, fscale, rows, cols, first_view, view_tab, box_tab, ray_tab, series,
                           blockIdx.x, blockIdx.y, blockIdx.z, S);
+}
+
+// Whether the odd series serves every voxel's angle from its tile centre's ray: a voxel lies
+// within h (the tile's half-diagonal) of its tile centre, which is at least d = R - rho_c from
+// the source (rho_c: the largest distance of a tile centre from the axis), so |tan delta| <=
+// h / sqrt(d^2 - h^2); at most 0.2 keeps the series' remainder below 1e-10 rad.  Wider angles
+// (short helix radii against the tile) take atan2f.
+int series_serves(const KParams &k) {
+    const double h = 0.5 * (kT - 1) * std::hypot(k.dx, k.dy);
+    double rc = 0.0;
+    for (int tx : {0, k.bp_tiles_x - 1})
+        for (int ty : {0, k.bp_tiles_y - 1}) {
+            const double xc = k.x_first + (tx * kT + 0.5 * (kT - 1)) * k.dx;
+            const double yc = k.y_first + (ty * kT + 0.5 * (kT - 1)) * k.dy;
+            rc = std::max(rc, std::hypot(xc, yc));
+        }
+    const double d = k.R - rc;
+    return d > h && h <= 0.2 * std::sqrt(d * d - h * h) ? 1 : 0;
 }
 
 template <int KZ, bool DET>
 void launch_bpT(bool fb, dim3 grid, hipStream_t s, const BpArgs &a, const float *gvol, void *gFout,
                 const double *fscale, int rows, int cols, long long first_view, const float4 *view,
-                const uint2 *boxes, const float4 *rays) {
+                const uint2 *boxes, const float4 *rays, int series) {
     // fb: HBM path for boxes beyond the LDS tile
     if (fb)
         hipLaunchKernelGGL((k_bpT_lds<KZ, true, DET>), grid, dim3(kNT), 0, s, a, gvol, gFout, fscale, rows,
-                           cols, first_view, view, boxes, rays);
+                           cols, first_view, view, boxes, rays, series);
     else
         hipLaunchKernelGGL((k_bpT_lds<KZ, false, DET>), grid, dim3(kNT), 0, s, a, gvol, gFout, fscale, rows,
-                           cols, first_view, view, boxes, rays);
+                           cols, first_view, view, boxes, rays, series);
 }
 
 // ----------------------------------------------------------------------------- fixed point
@@ -381,10 +410,11 @@ hipError_t launch_backproject_T(const KParams &k, const float *gvol, float *gFba
     const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
     const float4 *rays = reinterpret_cast<const float4 *>(k.tref);
     const bool fb = !k.bp_all_fit;
+    const int ser = series_serves(k);
     switch (k.bp_kz) {
-        case 8: launch_bpT<8, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
-        case 32: launch_bpT<32, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
-        default: launch_bpT<16, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        case 8: launch_bpT<8, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays, ser); break;
+        case 32: launch_bpT<32, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays, ser); break;
+        default: launch_bpT<16, false>(fb, grid, s, a, gvol, gFbar, nullptr, k.rows, k.cols, k.first_view, k.view, boxes, rays, ser); break;
     }
     return hipGetLastError();
 }
@@ -406,10 +436,11 @@ hipError_t launch_backproject_T_fixed(const KParams &k, const float *gvol, unsig
     const uint2 *boxes = reinterpret_cast<const uint2 *>(k.boxes);
     const float4 *rays = reinterpret_cast<const float4 *>(k.tref);
     const bool fb = !k.bp_all_fit;
+    const int ser = series_serves(k);
     switch (k.bp_kz) {
-        case 8: launch_bpT<8, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
-        case 32: launch_bpT<32, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
-        default: launch_bpT<16, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays); break;
+        case 8: launch_bpT<8, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays, ser); break;
+        case 32: launch_bpT<32, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays, ser); break;
+        default: launch_bpT<16, true>(fb, grid, s, a, gvol, gF64, S, k.rows, k.cols, k.first_view, k.view, boxes, rays, ser); break;
     }
     return hipGetLastError();
 }

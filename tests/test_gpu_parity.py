@@ -169,6 +169,38 @@ def test_recon_ragged_grids(shape):
         assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
 
 
+@pytest.mark.parametrize("R,degree", [(30.0, 7), (26.0, -1)])
+def test_wide_fan_geometries(R, degree):
+    """Short helix radii: a fan of +-0.79 rad takes the backprojector's general column
+    coordinate (degree-7 polynomial in tan^2, the instance a degree-4 fit cannot serve) and
+    +-0.96 rad the library atan2f (no polynomial of degree <= 8 meets the fit bound);
+    recon against the oracle at the bar, the adjoint against the oracle's transpose."""
+    dev = _dev()
+    wl = configs.make_workload(f"wide-fan-R{R:g}", feed=24.0, cols=96, rows=16, views_per_turn=144,
+                               turns=3, nxy=16, nz=12, dxy=2.0, slices_per_pitch=12, R=R, D=2.0 * R,
+                               phantom=configs.tiny(nxy=16).phantom, seed=7)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    print(f"[case] wide fan R = {R:g} mm", flush=True)
+    plan = K.Plan(geom, gr, device=0)
+    assert plan.info["atan_degree"] == degree
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    sino = phantom.project(ph, geom).astype(np.float32)
+    scan = O.Scan(geom)
+    ref, valid = O.recon(scan, gr, sino)
+    vol = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
+    peak = float(phantom.density(ph, _grid_points(gr)).max())
+    rel, mx = _report(f"wide fan R={R:g}", vol, ref, valid, peak)
+    assert valid.sum() > 0 and np.all(vol[~valid] == 0)
+    assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
+    rng = np.random.default_rng(8)
+    fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
+    got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev)).cpu().numpy()
+    refT = O.recon_T(scan, gr, fbar.astype(np.float64))
+    relT = np.linalg.norm(got - refT) / np.linalg.norm(refT)
+    print(f"[parity] wide fan R={R:g} adjoint vs oracle: rel-L2 {relT:.3e}", flush=True)
+    assert relT <= REL_L2
+
+
 def test_long_hulls_take_the_exact_fallback():
     """3000 views per turn: a workgroup's hull (the union of its voxels' PI windows over a
     pitch) spans ~4200 views, beyond the per-view group-word tables of both backprojectors,
