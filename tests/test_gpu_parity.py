@@ -180,25 +180,26 @@ def test_wide_fan_geometries(R, degree):
                                turns=3, nxy=16, nz=12, dxy=2.0, slices_per_pitch=12, R=R, D=2.0 * R,
                                phantom=configs.tiny(nxy=16).phantom, seed=7)
     geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
-    print(f"[case] wide fan R = {R:g} mm", flush=True)
-    plan = K.Plan(geom, gr, device=0)
-    assert plan.info["atan_degree"] == degree
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
     sino = phantom.project(ph, geom).astype(np.float32)
     scan = O.Scan(geom)
     ref, valid = O.recon(scan, gr, sino)
-    vol = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
     peak = float(phantom.density(ph, _grid_points(gr)).max())
-    rel, mx = _report(f"wide fan R={R:g}", vol, ref, valid, peak)
-    assert valid.sum() > 0 and np.all(vol[~valid] == 0)
-    assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
     rng = np.random.default_rng(8)
     fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
-    got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev)).cpu().numpy()
     refT = O.recon_T(scan, gr, fbar.astype(np.float64))
-    relT = np.linalg.norm(got - refT) / np.linalg.norm(refT)
-    print(f"[parity] wide fan R={R:g} adjoint vs oracle: rel-L2 {relT:.3e}", flush=True)
-    assert relT <= REL_L2
+    for kw in ({}, {"gpu_plan": True}):
+        print(f"[case] wide fan R = {R:g} mm, plan {kw}", flush=True)
+        plan = K.Plan(geom, gr, device=0, **kw)
+        assert plan.info["atan_degree"] == degree
+        vol = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
+        rel, mx = _report(f"wide fan R={R:g} {kw}", vol, ref, valid, peak)
+        assert valid.sum() > 0 and np.all(vol[~valid] == 0)
+        assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
+        got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev)).cpu().numpy()
+        relT = np.linalg.norm(got - refT) / np.linalg.norm(refT)
+        print(f"[parity] wide fan R={R:g} {kw} adjoint vs oracle: rel-L2 {relT:.3e}", flush=True)
+        assert relT <= REL_L2
 
 
 @pytest.mark.parametrize("variant", ["thin-slices", "thick-slices", "anisotropic-voxels"])
