@@ -202,20 +202,25 @@ def test_wide_fan_geometries(R, degree):
         assert relT <= REL_L2
 
 
-@pytest.mark.parametrize("variant", ["thin-slices", "thick-slices", "anisotropic-voxels"])
+@pytest.mark.parametrize("variant", ["thin-slices", "thick-slices", "anisotropic-voxels",
+                                     "partial-field-of-view"])
 def test_slice_and_voxel_shape_variants(variant):
     """Slice spacing far below the detector row spacing (rows per slice ~0.1: many slices
     share a row in the adjoint's row merging), far above it (~3 rows per slice: the walk
-    skips rows), and non-square voxels (dx != dy): recon against the oracle at the bar, the
-    adjoint against the oracle's transpose."""
+    skips rows), non-square voxels (dx != dy), and a fan narrower than the grid (field of
+    view radius 14.9 mm against 21.2 mm grid corners: a third of the voxels invalid, their
+    lanes idle inside the tiles, the projections truncated): recon against the oracle at the
+    bar, the adjoint against the oracle's transpose."""
     dev = _dev()
-    spp = {"thin-slices": 96, "thick-slices": 3, "anisotropic-voxels": 12}[variant]
-    nz = {"thin-slices": 40, "thick-slices": 6, "anisotropic-voxels": 16}[variant]
+    spp = {"thin-slices": 96, "thick-slices": 3}.get(variant, 12)
+    nz = {"thin-slices": 40, "thick-slices": 6}.get(variant, 16)
     wl = configs.tiny(nxy=16, nz=nz, cols=48, rows=8, views_per_turn=72, turns=5, feed=24.0,
                       dxy=2.0, slices_per_pitch=spp)
     geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
     if variant == "anisotropic-voxels":
         gr.update(nx=12, ny=20, dx=2.6, dy=1.5, x_first=-0.5 * 11 * 2.6, y_first=-0.5 * 19 * 1.5)
+    if variant == "partial-field-of-view":
+        geom["dalpha"] *= 0.7
     print(f"[case] {variant}: dz {gr['dz']:.3f} mm, dw {geom['dw']:.3f} mm", flush=True)
     plan = K.Plan(geom, gr, device=0)
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
@@ -226,6 +231,8 @@ def test_slice_and_voxel_shape_variants(variant):
     peak = float(phantom.density(ph, _grid_points(gr)).max())
     rel, mx = _report(variant, vol, ref, valid, peak)
     assert valid.sum() > 0 and np.all(vol[~valid] == 0)
+    if variant == "partial-field-of-view":
+        assert 0 < int((~valid).sum()) < valid.size
     assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
     rng = np.random.default_rng(9)
     fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
