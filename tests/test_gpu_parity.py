@@ -243,6 +243,38 @@ def test_slice_and_voxel_shape_variants(variant):
     assert relT <= REL_L2
 
 
+@pytest.mark.parametrize("n_psi", [5, 64, 200])
+def test_kappa_line_counts(n_psi):
+    """Other numbers of kappa-lines than the default 2 rows + 1: few (5), even (64: the FFT
+    pairs kappa rows two per transform, the matrix-core tiles group 16 lines), many (200);
+    both Hilbert paths against the oracle with the same count, and the adjoint against the
+    oracle's transpose."""
+    dev = _dev()
+    wl = configs.tiny(nxy=16, nz=12, cols=48, rows=8, views_per_turn=72, turns=5, feed=24.0,
+                      dxy=2.0, slices_per_pitch=12)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    print(f"[case] n_psi = {n_psi}", flush=True)
+    ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
+    sino = phantom.project(ph, geom).astype(np.float32)
+    scan = O.Scan(geom, n_psi)
+    ref, valid = O.recon(scan, gr, sino)
+    peak = float(phantom.density(ph, _grid_points(gr)).max())
+    for mode in (1, 2):
+        plan = K.Plan(geom, gr, device=0, n_psi=n_psi, hilbert_mode=mode)
+        assert plan.info["n_psi"] == n_psi
+        vol = K.recon(plan, torch.from_numpy(sino).to(dev)).cpu().numpy()
+        rel, mx = _report(f"n_psi {n_psi} hilbert_mode {mode}", vol, ref, valid, peak)
+        assert np.all(vol[~valid] == 0)
+        assert rel <= REL_L2 and mx <= MAX_ABS_OF_PEAK * peak
+    rng = np.random.default_rng(10)
+    fbar = rng.normal(size=(gr["nz"], gr["ny"], gr["nx"])).astype(np.float32)
+    got = K.recon_backward(plan, torch.from_numpy(fbar).to(dev)).cpu().numpy()
+    refT = O.recon_T(scan, gr, fbar.astype(np.float64))
+    relT = np.linalg.norm(got - refT) / np.linalg.norm(refT)
+    print(f"[parity] n_psi {n_psi} adjoint vs oracle: rel-L2 {relT:.3e}", flush=True)
+    assert relT <= REL_L2
+
+
 def test_long_hulls_take_the_exact_fallback():
     """3000 views per turn: a workgroup's hull (the union of its voxels' PI windows over a
     pitch) spans ~4200 views, beyond the per-view group-word tables of both backprojectors,
