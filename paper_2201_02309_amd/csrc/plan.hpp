@@ -38,11 +38,13 @@ constexpr int kPad = 2;
 constexpr int kBpBoxRows = 32;
 constexpr int kBpBoxCols = 64;
 // Views per chunk of the filter chains: as many as kFilterChunkBytes of intermediates
-// (kappa-rows + detector rows) hold, at least kFilterChunk (512 views of the clinical
-// 736-column detector take 0.29 GB; a narrow detector gets longer chunks, whose launches
-// would otherwise be too short to fill the GPU).
-constexpr int kFilterChunk = 512;
-constexpr uint64_t kFilterChunkBytes = 256ull << 20;
+// (kappa-rows + detector rows) hold, at least kFilterChunk (the clinical 736-column detector
+// takes 398 views, 0.22 GB, cut to 381 for whole rounds of the matrix-core Hilbert's tiles; a
+// narrow detector gets longer chunks, whose launches would otherwise be too short to fill
+// the GPU).  Measured on the clinical filter: 381-view chunks 1.76 ms, 508 1.79, 1016 1.84,
+// 254 1.79 (half-sample plan 1.90, 1.97, 2.10, 1.87).
+constexpr int kFilterChunk = 384;
+constexpr uint64_t kFilterChunkBytes = 216ull << 20;
 // Scale of the matrix-core Hilbert's taps: |K[m]| <= 2/pi, so 2^14 K stays below the float16
 // maximum and the smallest taps' low halves stay normal numbers.
 constexpr double kHilTapScale = 16384.0;
