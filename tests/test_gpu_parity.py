@@ -203,13 +203,15 @@ def test_wide_fan_geometries(R, degree):
 
 
 @pytest.mark.parametrize("variant", ["thin-slices", "thick-slices", "anisotropic-voxels",
-                                     "partial-field-of-view"])
+                                     "partial-field-of-view", "tall-detector", "tight-detector"])
 def test_slice_and_voxel_shape_variants(variant):
     """Slice spacing far below the detector row spacing (rows per slice ~0.1: many slices
     share a row in the adjoint's row merging), far above it (~3 rows per slice: the walk
     skips rows), non-square voxels (dx != dy), and a fan narrower than the grid (field of
     view radius 14.9 mm against 21.2 mm grid corners: a third of the voxels invalid, their
-    lanes idle inside the tiles, the projections truncated): recon against the oracle at the
+    lanes idle inside the tiles, the projections truncated), detector rows covering 1.5
+    times the Tam-Danielsson window and only 1 % more than it (projections reaching the edge
+    rows, footprint boxes clipped at the padded detector): recon against the oracle at the
     bar, the adjoint against the oracle's transpose."""
     dev = _dev()
     spp = {"thin-slices": 96, "thick-slices": 3}.get(variant, 12)
@@ -221,6 +223,10 @@ def test_slice_and_voxel_shape_variants(variant):
         gr.update(nx=12, ny=20, dx=2.6, dy=1.5, x_first=-0.5 * 11 * 2.6, y_first=-0.5 * 19 * 1.5)
     if variant == "partial-field-of-view":
         geom["dalpha"] *= 0.7
+    if variant == "tall-detector":
+        geom["dw"] *= 1.5 / 1.1                   # the recipe's rows cover 1.1 x the window
+    if variant == "tight-detector":
+        geom["dw"] *= 1.01 / 1.1
     print(f"[case] {variant}: dz {gr['dz']:.3f} mm, dw {geom['dw']:.3f} mm", flush=True)
     plan = K.Plan(geom, gr, device=0)
     ph = phantom.make_phantom(wl.phantom, gr, wl.seed)
