@@ -129,3 +129,15 @@ def test_adjoint_parity_non_commensurate_grid():
     wl, geom, gr = _non_commensurate()
     gr = dict(gr, nx=12, ny=12, x_first=-11.0, y_first=-11.0, nz=16)
     _adjoint_parity("non-commensurate dz 1.7", geom, gr, 33)
+
+
+def test_large_helix_offsets():
+    """A helix far from the origin: lambda0 = 100.3 rad, z0 = 2500 mm and the first view at
+    37.1 rad (the grid at ~2.5 m height); every coordinate the kernels see in float32 is
+    relative to the pitch or the view, so the bars are the same: recon and adjoint."""
+    wl = configs.with_helix_offsets(
+        configs.tiny(nxy=16, nz=16, cols=48, rows=8, views_per_turn=72, turns=5, feed=24.0,
+                     dxy=2.0, slices_per_pitch=12), lambda0=100.3, z0=2500.0, lambda_first=37.1)
+    geom, gr = wl.geom.as_dict(), wl.grid.as_dict()
+    _recon_parity("large offsets", geom, gr, wl.phantom, wl.seed)
+    _adjoint_parity("large offsets", geom, gr, 32)
