@@ -24,35 +24,37 @@ constexpr int kBrUnroll = 12;     // rows per thread with every load issued firs
 // One thread per (detector row, column) takes a run of consecutive views, so each sinogram
 // sample comes from HBM about once: the run's samples (plus one view on each side) are loaded
 // into registers, every load issued before the first use (0.03 ms faster over the clinical
-// filter than a walk keeping the previous / current / next views), and the neighbouring
-// columns of each view hit the cache.
+// filter than a walk keeping the previous / current / next views).  The neighbouring
+// columns' samples come from the neighbouring lanes (wave shuffles): a wave loads 64
+// consecutive columns and writes the 62 inner ones, its first and last lanes loading the
+// halo columns only.
+constexpr int kDerivColsPerWave = 62;
 __global__ __launch_bounds__(kElemThreads) void k_deriv_lw(KParams p, const float *__restrict__ sino,
                                                            float *__restrict__ g2) {
-    const int c = blockIdx.x * kElemThreads + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int c = (blockIdx.x * (kElemThreads / 64) + (threadIdx.x >> 6)) * kDerivColsPerWave + lane - 1;
+    const bool inc = c >= 0 && c < p.cols;                      // a column of the detector
+    const bool out = inc && lane > 0 && lane < 63;              // written by this lane
     const int r = blockIdx.y;
     const long long i0 = (long long)blockIdx.z * kDerivRun;   // first filtered view of the run
-    if (c >= p.cols) return;
     const long long i1 = i0 + kDerivRun < p.n_filt ? i0 + kDerivRun : p.n_filt;
     const size_t rc = (size_t)p.rows * p.cols;
-    const float *col = sino + (size_t)r * p.cols + c;         // sample (view 0, r, c)
+    const float *col = sino + (size_t)r * p.cols + (inc ? c : 0);   // sample (view 0, r, c)
     const float w = p.lw[r];
     long long n = p.first_view + i0;                           // 1 <= n <= n_views-2
     // all of the run's loads issued before the first use
-    float x[kDerivRun + 2], lf[kDerivRun], rt[kDerivRun];
+    float x[kDerivRun + 2];
     const int nr = (int)(i1 - i0);
 #pragma unroll
-    for (int j = 0; j < kDerivRun + 2; ++j) x[j] = j < nr + 2 ? col[(size_t)(n - 1 + j) * rc] : 0.0f;
+    for (int j = 0; j < kDerivRun + 2; ++j) x[j] = (inc && j < nr + 2) ? col[(size_t)(n - 1 + j) * rc] : 0.0f;
 #pragma unroll
     for (int j = 0; j < kDerivRun; ++j) {
-        const float *g0 = col + (size_t)(n + j) * rc;
-        lf[j] = (j < nr && c > 0) ? g0[-1] : 0.0f;
-        rt[j] = (j < nr && c + 1 < p.cols) ? g0[1] : 0.0f;
-    }
-#pragma unroll
-    for (int j = 0; j < kDerivRun; ++j)
-        if (j < nr)
+        // columns c - 1 and c + 1 of view n + j (zero outside the detector: those lanes hold 0)
+        const float lf = __shfl_up(x[j + 1], 1, 64), rt = __shfl_down(x[j + 1], 1, 64);
+        if (out && j < nr)
             g2[(size_t)(i0 + j) * rc + (size_t)r * p.cols + c] =
-                w * ((x[j + 2] - x[j]) * p.inv_2dlam + (rt[j] - lf[j]) * p.inv_2dalpha);
+                w * ((x[j + 2] - x[j]) * p.inv_2dlam + (rt - lf) * p.inv_2dalpha);
+    }
 }
 
 // Half-sample derivative: filtered view i (cell-centre view n = first_view + i, between
@@ -61,27 +63,31 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_lw(KParams p, const floa
 // loads the two columns of its run of views (plus the next view) before the first use.
 __global__ __launch_bounds__(kElemThreads) void k_deriv_lw_half(KParams p, const float *__restrict__ sino,
                                                                 float *__restrict__ g2) {
-    const int c = blockIdx.x * kElemThreads + threadIdx.x;
+    // a wave loads 64 consecutive sinogram columns and writes the 63 cells between them; the
+    // right column of each cell comes from the next lane (wave shuffle)
+    const int lane = threadIdx.x & 63;
+    const int c = (blockIdx.x * (kElemThreads / 64) + (threadIdx.x >> 6)) * (kDerivColsPerWave + 1) + lane;
+    const bool inc = c < p.sino_cols;                          // a sinogram column
+    const bool out = lane < 63 && c < p.cols;                  // a cell written by this lane
     const int r = blockIdx.y;
     const long long i0 = (long long)blockIdx.z * kDerivRun;
-    if (c >= p.cols) return;
     const long long i1 = i0 + kDerivRun < p.n_filt ? i0 + kDerivRun : p.n_filt;
     const size_t src = (size_t)p.rows * p.sino_cols;          // sinogram view stride
     const size_t rc = (size_t)p.rows * p.cols;
-    const float *col = sino + (size_t)r * p.sino_cols + c;    // sinogram (view 0, r, c)
+    const float *col = sino + (size_t)r * p.sino_cols + (inc ? c : 0);   // sinogram (view 0, r, c)
     const float w = p.lw[r];
     long long n = p.first_view + i0;                          // 0 <= n, n+1 <= sino_views-1
     // all of the run's loads issued before the first use
-    float x0[kDerivRun + 1], x1[kDerivRun + 1];
+    float x0[kDerivRun + 1];
     const int nr = (int)(i1 - i0);
 #pragma unroll
-    for (int j = 0; j < kDerivRun + 1; ++j) {
-        x0[j] = j < nr + 1 ? col[(size_t)(n + j) * src] : 0.0f;
-        x1[j] = j < nr + 1 ? col[(size_t)(n + j) * src + 1] : 0.0f;
-    }
+    for (int j = 0; j < kDerivRun + 1; ++j) x0[j] = (inc && j < nr + 1) ? col[(size_t)(n + j) * src] : 0.0f;
+    float x1[kDerivRun + 1];
+#pragma unroll
+    for (int j = 0; j < kDerivRun + 1; ++j) x1[j] = __shfl_down(x0[j], 1, 64);
 #pragma unroll
     for (int j = 0; j < kDerivRun; ++j) {
-        if (j < nr) {
+        if (out && j < nr) {
             const float dl = ((x0[j + 1] - x0[j]) + (x1[j + 1] - x1[j])) * p.inv_2dlam;
             const float da = ((x1[j] - x0[j]) + (x1[j + 1] - x0[j + 1])) * p.inv_2dalpha;
             g2[(size_t)(i0 + j) * rc + (size_t)r * p.cols + c] = w * (dl + da);
@@ -590,12 +596,16 @@ __global__ __launch_bounds__(kElemThreads) void k_deriv_T_half(KParams p, const 
 hipError_t launch_filter(const KParams &k, const float *sino, float *g2, float *g4, float *gF,
                          float *vmax, hipStream_t s) {
     if (k.n_filt <= 0) return hipSuccess;
-    const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
     const unsigned runs = (unsigned)((k.n_filt + kDerivRun - 1) / kDerivRun);
-    if (k.half)
-        hipLaunchKernelGGL(k_deriv_lw_half, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
-    else
-        hipLaunchKernelGGL(k_deriv_lw, dim3(cb, k.rows, runs), dim3(kElemThreads), 0, s, k, sino, g2);
+    if (k.half) {
+        const int per_block = (kDerivColsPerWave + 1) * (kElemThreads / 64);
+        hipLaunchKernelGGL(k_deriv_lw_half, dim3((k.cols + per_block - 1) / per_block, k.rows, runs),
+                           dim3(kElemThreads), 0, s, k, sino, g2);
+    } else {
+        const int per_block = kDerivColsPerWave * (kElemThreads / 64);
+        hipLaunchKernelGGL(k_deriv_lw, dim3((k.cols + per_block - 1) / per_block, k.rows, runs),
+                           dim3(kElemThreads), 0, s, k, sino, g2);
+    }
     if (k.hil_mode == KATS_HILBERT_MFMA) {
         const dim3 grid((unsigned)((k.n_filt + kRebinViews - 1) / kRebinViews), (unsigned)((k.cols + kDRThreads - 1) / kDRThreads),
                         (unsigned)((k.n_psi + kRebinLines - 1) / kRebinLines));
