@@ -555,20 +555,32 @@ __global__ __launch_bounds__(kColWave) void k_fr_lw_T(KParams p, const float *__
 //   (g2bar[n-1] - g2bar[n+1]) / (2 dlambda) + (g2bar[c-1] - g2bar[c+1]) / (2 dalpha)
 // over the filtered views (views outside contribute 0).  Every sinogram sample is written.
 __global__ __launch_bounds__(kElemThreads) void k_deriv_T(KParams p, const float *__restrict__ g2bar,
-                                                          float *__restrict__ gsino, long long n0) {
-    const long long n = n0 + blockIdx.x;            // sinogram view
+                                                          float *__restrict__ gsino, long long n0, long long count) {
+    // one thread per (row, column, run of kDerivRun sinogram views): the run's samples of
+    // g2-bar (one view each side more) loaded first, the neighbouring columns from the
+    // neighbouring lanes (a wave loads 64 columns and writes the 62 inner ones)
+    const int lane = threadIdx.x & 63;
+    const int c = (blockIdx.z * (kElemThreads / 64) + (threadIdx.x >> 6)) * kDerivColsPerWave + lane - 1;
+    const bool inc = c >= 0 && c < p.cols;
+    const bool out = inc && lane > 0 && lane < 63;
     const int r = blockIdx.y;
-    const int c = blockIdx.z * kElemThreads + threadIdx.x;
-    if (c >= p.cols) return;
+    const long long m0 = (long long)blockIdx.x * kDerivRun;    // first view of the run within the call
+    const int nr = (int)(count - m0 < kDerivRun ? count - m0 : kDerivRun);
     const size_t rc = (size_t)p.rows * p.cols;
-    auto at = [&](long long view, int col) -> float {
-        const long long i = view - p.first_view;
-        if (i < 0 || i >= p.n_filt || col < 0 || col >= p.cols) return 0.0f;
-        return g2bar[(size_t)i * rc + (size_t)r * p.cols + col];
-    };
-    const float vl = (at(n - 1, c) - at(n + 1, c)) * p.inv_2dlam;
-    const float va = (at(n, c - 1) - at(n, c + 1)) * p.inv_2dalpha;
-    gsino[(size_t)n * rc + (size_t)r * p.cols + c] = vl + va;
+    const float *col = g2bar + (size_t)r * p.cols + (inc ? c : 0);
+    float x[kDerivRun + 2];                     // filtered views n - 1 .. n + kDerivRun, n = n0 + m0
+#pragma unroll
+    for (int j = 0; j < kDerivRun + 2; ++j) {
+        const long long i = n0 + m0 - 1 + j - p.first_view;
+        x[j] = (inc && j < nr + 2 && i >= 0 && i < p.n_filt) ? col[(size_t)i * rc] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < kDerivRun; ++j) {
+        const float lf = __shfl_up(x[j + 1], 1, 64), rt = __shfl_down(x[j + 1], 1, 64);
+        if (out && j < nr)
+            gsino[(size_t)(n0 + m0 + j) * rc + (size_t)r * p.cols + c] =
+                (x[j] - x[j + 2]) * p.inv_2dlam + (lf - rt) * p.inv_2dalpha;
+    }
 }
 
 // Transpose of the half-sample derivative (LW^T is applied by k_fr_lw_T): sinogram
@@ -639,9 +651,10 @@ hipError_t launch_deriv_T(const KParams &k, const float *g2bar, float *gsino, lo
         hipLaunchKernelGGL(k_deriv_T_half, dim3((unsigned)count, k.rows, cbs), dim3(kElemThreads), 0, s, k,
                            g2bar, gsino, n0);
     } else {
-        const int cb = (k.cols + kElemThreads - 1) / kElemThreads;
-        hipLaunchKernelGGL(k_deriv_T, dim3((unsigned)count, k.rows, cb), dim3(kElemThreads), 0, s, k, g2bar,
-                           gsino, n0);
+        const int per_block = kDerivColsPerWave * (kElemThreads / 64);
+        hipLaunchKernelGGL(k_deriv_T, dim3((unsigned)((count + kDerivRun - 1) / kDerivRun), k.rows,
+                                           (unsigned)((k.cols + per_block - 1) / per_block)),
+                           dim3(kElemThreads), 0, s, k, g2bar, gsino, n0, count);
     }
     return hipGetLastError();
 }
