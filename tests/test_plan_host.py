@@ -248,3 +248,32 @@ def test_tables_bit_exact_with_helix_offsets():
         s = k * scan.Nv
         f_valid[sl] = O.valid_mask(scan, tab["nf"][js] + s, tab["nl"][js] + s, tab["fov"][js])
     assert np.array_equal(p.export("valid").astype(bool), f_valid) and f_valid.sum() > 1000
+
+
+@pytest.mark.parametrize("case", ["parity", "parity half-sample", "sparse", "clinical", "offsets",
+                                  "wide fan R=30", "few kappa-lines"])
+def test_backward_rebinning_line_rises_along_each_column(case):
+    """The backward-rebinning kappa-line index k0 never decreases from one detector row to
+    the next (psi_hat rises with w on the monotone branch of w_kappa, Sec. II backward
+    height rebinning); the adjoint's BR^T kernel writes each kappa-line once on that basis."""
+    kw = {}
+    if case.startswith("parity"):
+        wl = configs.config1()
+        kw = {"half_sample": case.endswith("half-sample")}
+    elif case == "sparse":
+        wl = configs.config3(0)
+    elif case == "clinical":
+        wl = configs.config2()
+    elif case == "offsets":
+        wl = configs.with_helix_offsets(configs.config1())
+    elif case == "wide fan R=30":
+        wl = configs.make_workload("wide-fan-R30", feed=24.0, cols=96, rows=16, views_per_turn=144,
+                                   turns=3, nxy=16, nz=12, dxy=2.0, slices_per_pitch=12, R=30.0,
+                                   D=60.0, phantom=configs.tiny(nxy=16).phantom, seed=7)
+    else:
+        wl = configs.tiny()
+        kw = {"n_psi": 5}
+    p = pk.Plan(wl.geom.as_dict(), wl.grid.as_dict(), bind=False, **kw)
+    k0 = p.export("br_kappa").astype(np.int64)
+    assert np.all(np.diff(k0, axis=0) >= 0)
+    assert k0.min() >= 0 and k0.max() <= p.info["n_psi"] - 2
